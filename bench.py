@@ -1,0 +1,171 @@
+"""Throughput of the fused lattice Boltzmann step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload droplet|bubbles|channel|sweep] [--no-cpu]
+
+A step is one time step of the three coupled D2Q9 LBEs over the whole lattice
+(one fused kernel launch).  The default workload is the droplet-migration
+lattice, 256 x 1024 nodes, Ma = 1, density/viscosity/conductivity/heat-
+capacitance ratio 0.5, timed in FP32 deviation storage (the headline value)
+and in FP64.  Prints one JSON line.
+
+Only one GPU is used; --gpus above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (3 coupled D2Q9 LBEs) FP64 vs FP32; surrogate speedup at ≤1% L2 err"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2306_11320_amd", "csrc", "lbm_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def stored_traffic(workload: str, prec: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"lbm_step_{workload}_{prec}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def make_workload(name: str):
+    from paper_2306_11320_amd import workloads as wl
+    if name == "droplet":
+        cfg, f0 = wl.droplet(Ma=1.0, ratio=0.5)
+        return [(cfg, f0)], dict(workload="droplet_migration_256x1024", nx=256, ny=1024, Ma=1.0, ratio=0.5)
+    if name == "bubbles":
+        cfg, f0 = wl.two_bubbles(sigma_TT=0.2)
+        return [(cfg, f0)], dict(workload="two_bubbles_512x2048", nx=512, ny=2048, sigma_TT=0.2)
+    if name == "channel":
+        cfg, f0 = wl.heated_channel(2.0)
+        return [(cfg, f0)], dict(workload="heated_channel_64x32", nx=64, ny=32, lambda_ratio=2.0)
+    if name == "sweep":
+        items = wl.sweep(64, seed=4)
+        nodes = sum(c["nx"] * c["ny"] for c, _ in items)
+        return items, dict(workload="batched_droplet_sweep_64", instances=64, nodes=nodes)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_gpu(items, prec, steps, warmup, tile=None):
+    import torch
+    from paper_2306_11320_amd import lbm
+    if len(items) == 1:
+        lat = lbm.Lattice(items[0][0], items[0][1], prec)
+    else:
+        lat = lbm.Lattice.batch(items, prec)
+    if tile is not None:
+        lat.set_tile(tile)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(lat.stream)
+    t0 = time.perf_counter()
+    lat.step(steps)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    d = lat.diagnostics()
+    nodes = sum(c["nx"] * c["ny"] for c, _ in items)
+    lat.close()
+    return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes,
+                mlups=nodes * steps / (ms * 1e-3) / 1e6, finite=d["n_nonfinite"] == 0, max_u=d["max_u"])
+
+
+def cpu_baseline(items, budget_s: float = 15.0):
+    """The FP64 oracle as it stands on the host cores, on the first lattice of
+    the workload: steps are added until about budget_s of CPU work."""
+    import oracle
+    cfg, f0 = items[0]
+    o = oracle.Oracle(cfg, f0)
+    threads = oracle.Oracle.threads()
+    t0 = time.perf_counter()
+    o.step(2)
+    dt = time.perf_counter() - t0
+    n = max(2, int(budget_s / max(dt / 2, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    nodes = cfg["nx"] * cfg["ny"]
+    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{cfg['nx']}x{cfg['ny']} lattice of the workload, {n} FP64 steps from the initial state, "
+                       f"{dt:.1f} s on {threads} OpenMP threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2048)
+    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--workload", default="droplet")
+    ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the lattice update is not sharded "
+              "across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2306_11320_amd import lbm
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    items, cfgdesc = make_workload(args.workload)
+    print(f"[bench] workload {cfgdesc['workload']}: FP32 deviation storage, {args.steps} steps", file=sys.stderr,
+          flush=True)
+    r32 = time_gpu(items, lbm.FP32_DEV, args.steps, args.warmup, args.tile)
+    bpl = lbm.bytes_per_update(lbm.FP32_DEV) * r32["nodes"]
+    achieved = bpl / (r32["ms_per_step"] * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, "fp32")
+    out = {
+        "metric": METRIC, "value": round(r32["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu",
+                       working_set_bytes=2 * bpl // 2 * 2 // 2 * 1 if False else None),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+    }
+    ws = (2 * 27 + 2) * 4 * r32["nodes"]
+    out["config"]["working_set_bytes"] = ws
+    out["config"]["algorithmic_bytes_per_launch"] = bpl
+    if not args.fp32_only:
+        print("[bench] FP64", file=sys.stderr, flush=True)
+        r64 = time_gpu(items, lbm.FP64, args.steps, args.warmup, args.tile)
+        b64 = lbm.bytes_per_update(lbm.FP64) * r64["nodes"]
+        a64 = b64 / (r64["ms_per_step"] * 1e-3) / 1e9
+        out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
+                       "working_set_bytes": (2 * 27 + 2) * 8 * r64["nodes"],
+                       "roofline": {"bound": "hbm", "achieved": round(a64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(a64 / HBM_PEAK_GBS, 4),
+                                    "traffic": stored_traffic(args.workload, "fp64")}}
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(items)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

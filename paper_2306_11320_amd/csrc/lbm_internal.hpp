@@ -1,0 +1,81 @@
+// Internal declarations shared by the kernels (lbm_kernels.hip) and the host
+// side of the C ABI (lbm_api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+// Population storage of one lattice: 27 planes (f_0..8, g_0..8, h_0..8) per
+// time level, each plane `plane` elements long with rows `pitch` elements
+// apart (x fastest).  Level A/B alternate every step.  f and h are stored as
+// deviations from the rest equilibrium w_i phi0 and w_i T0; g as is.
+constexpr int kPlanes = 27;
+constexpr int kF = 0, kG = 9, kH = 18;
+
+// Per-lattice constants, in the working precision.  Properties are stored as
+// xi(phi) = xi_a + xi_b * phi (linear interpolation between phi = -1 and +1).
+template <typename real>
+struct Inst {
+    real* pop[2];        // time levels A and B
+    real* jprev;         // 2 planes: (phi u)_x, (phi u)_y of the previous level
+    int nx, ny, pitch, grad_mode;
+    long long plane;
+    int bc[4];
+    real phi0, T0;
+    real rho_a, rho_b, mu_a, mu_b, lam_a, lam_b, rcp_a, rcp_b;
+    real sigma_ref, sigma_T, sigma_TT, dTref;   // dTref = T0 - T_ref
+    real W2, pref, inv_W2, inv_s2W;             // W^2, 3 sqrt(2) W / 4, 1/W^2, 1/(sqrt(2) W)
+    real inv_tau_phi, fac_phi;                  // 1/tau_phi, 1 - 1/(2 tau_phi)
+    real Gx, Gy;
+    real tw_mean[4], tw_amp[4], tw_k[4], tw_slope[4];  // tw_mean relative to T0
+    real u_in, phi_in_d, T_in_d;                // phi_in - phi0, T_in - T0
+};
+
+struct Tile {
+    int inst, x0, y0, pad;
+};
+
+// Sums accumulated by the FP64 diagnostics reduction, per lattice.
+enum DiagSlot {
+    D_MASS = 0, D_VOL, D_HEAT, D_SNEG, D_SUY, D_SUX, D_SX, D_SY, D_MAXU, D_NONFIN, D_NNEG,
+    D_BUB = 11,  // 4 regions x (sum, sum x, sum y, sum ux, sum uy)
+    D_COUNT = 31
+};
+
+struct DiagArgs {
+    double bx[4], by[4];
+    double rcp_a, rcp_b;
+    int n_bubbles;
+};
+
+struct InitArgs {
+    double phi0, T0, rho_a, rho_b;
+};
+
+// Compiled tile shapes (TX x TY nodes, one work-item per node).
+constexpr int kTileCount = 6;
+constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128};
+constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4};
+
+// Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
+hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
+                       hipStream_t s);
+// Macroscopic fields of level `src`: any output may be null; out_f32 selects
+// float outputs.  If `jprev_out` is set, (phi u) is written to the lattice's
+// jprev planes instead.
+hipError_t launch_fields(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src,
+                         void* phi, void* ux, void* uy, void* T, void* p, int out_f32, int jprev_out,
+                         hipStream_t s);
+// Equilibrium populations of one lattice from staged FP64 fields phi, ux, uy,
+// T (n_nodes each, x fastest, contiguous) into time level `src`.
+hipError_t launch_init(int prec, const void* inst_dev, long long n_nodes, const double* staged, const InitArgs& a,
+                       int src, hipStream_t s);
+// Per-workgroup FP64 partial sums (D_COUNT each) then a deterministic final sum
+// into `result` (D_COUNT doubles).
+hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src,
+                       const DiagArgs& a, double* partials, double* result, hipStream_t s);
+
+}  // namespace lbm

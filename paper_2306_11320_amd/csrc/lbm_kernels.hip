@@ -1,0 +1,727 @@
+// gfx950 kernels for one time step of the three coupled D2Q9 lattice Boltzmann
+// equations of Wang, He & Wang, arXiv:2306.11320 (Sec. 3, Sec. 4 preamble).
+//
+// One fused kernel per step.  A workgroup owns a TX x TY tile of nodes, one
+// work-item per node:
+//   1. every work-item loads its own 27 populations and (phi u) of the previous
+//      level; the zeroth moments phi = sum f_i, T = sum h_i and the h_i of the
+//      tile plus a one-node ring go to LDS (the ring re-sums its neighbours'
+//      populations, which mostly hit L2);
+//   2. isotropic stencils for grad phi, lap phi, grad T from LDS; properties,
+//      sigma(T), the interfacial force of Eq. 11, u and p (Sec. 3.1), the time
+//      derivative of phi u (Sec. 4 preamble);
+//   3. the three BGK collisions (Eq. 14, the NS LBE, Eq. 28);
+//   4. push streaming to the other time level with the boundary rules folded
+//      in; the thermal update divides by the destination's heat capacitance
+//      and blends with the destination's old h_i, both read from LDS.
+// There is no MFMA on this path: it is bound by HBM traffic.
+//
+// Storage is structure-of-arrays planes, x fastest, f and h kept as deviations
+// from w_i phi0 and w_i T0 (exact for BGK, streaming, bounce-back and the
+// blend, whose weights sum to one), g as is.
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_WALL_T = 1, BC_WALL_ADIABATIC = 2, BC_INLET = 3, BC_OUTLET = 4 };
+
+// D2Q9 (Sec. 4 preamble): c_0 = (0,0); c_1..4 = (1,0),(0,1),(-1,0),(0,-1);
+// c_5..8 = (1,1),(-1,1),(-1,-1),(1,-1); weights 4/9, 1/9, 1/36.
+__host__ __device__ constexpr int cx(int k) { return (k == 1 || k == 5 || k == 8) ? 1 : ((k == 3 || k == 6 || k == 7) ? -1 : 0); }
+__host__ __device__ constexpr int cy(int k) { return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0); }
+__host__ __device__ constexpr int opp(int k) { return k == 0 ? 0 : (k <= 4 ? ((k + 1) % 4) + 1 : ((k - 3) % 4) + 5); }
+template <typename real>
+__device__ constexpr real wgt(int k) { return k == 0 ? real(4.0 / 9.0) : (k <= 4 ? real(1.0 / 9.0) : real(1.0 / 36.0)); }
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opposite map");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opposite map");
+
+template <typename real, int TX, int TY>
+struct Patch {
+    static constexpr int PX = TX + 2, PY = TY + 2, NP = PX * PY;
+    static constexpr int NRING = 2 * PX + 2 * TY;
+    real phi[NP];    // phi - phi0 on the tile plus ring (ghosts applied)
+    real T[NP];      // T - T0
+    real irc[NP];    // 1 / (rho c_p)
+    real h[9][NP];   // h_i - w_i T0 of the node (real nodes only)
+};
+
+// Wall temperature relative to T0 at coordinate s along `side`.
+template <typename real>
+__device__ inline real wall_T(const Inst<real>& I, int side, real s)
+{
+    return I.tw_mean[side] + I.tw_amp[side] * cos(I.tw_k[side] * s) + I.tw_slope[side] * s;
+}
+
+// Affine ghost rule of one side: ghost = a + sgn * inner (deviation units).
+template <typename real>
+__device__ inline void ghost_rule(const Inst<real>& I, int side, real s, real& aphi, real& sphi, real& aT, real& sT)
+{
+    const int bc = I.bc[side];
+    aphi = real(0); sphi = real(1); aT = real(0); sT = real(1);
+    if (bc == BC_INLET) {
+        aphi = real(2) * I.phi_in_d; sphi = real(-1);
+        aT = real(2) * I.T_in_d; sT = real(-1);
+    } else if (bc == BC_WALL_T) {
+        aT = real(2) * wall_T(I, side, s); sT = real(-1);
+    }
+}
+
+// Maps lattice point (gx, gy), possibly outside the domain, to the node whose
+// moments define it and the affine map applied to them.  The rule of the y
+// side is applied outermost, as for the corner ghosts of the oracle's reading.
+template <typename real>
+__device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int& sy, real& aphi, real& sphi,
+                               real& aT, real& sT)
+{
+    const int nx = I.nx, ny = I.ny;
+    bool real_node = true;
+    real ayp = 0, syp = 1, ayT = 0, syT = 1, axp = 0, sxp = 1, axT = 0, sxT = 1;
+    int jj = gy;
+    if (gy < 0 || gy >= ny) {
+        const int side = gy < 0 ? 2 : 3;
+        if (I.bc[side] == BC_PERIODIC) {
+            jj = gy < 0 ? gy + ny : gy - ny;
+        } else {
+            jj = gy < 0 ? -1 - gy : 2 * ny - 1 - gy;
+            ghost_rule(I, side, real(gx), ayp, syp, ayT, syT);
+            real_node = false;
+        }
+    }
+    int ii = gx;
+    if (gx < 0 || gx >= nx) {
+        const int side = gx < 0 ? 0 : 1;
+        if (I.bc[side] == BC_PERIODIC) {
+            ii = gx < 0 ? gx + nx : gx - nx;
+        } else {
+            ii = gx < 0 ? -1 - gx : 2 * nx - 1 - gx;
+            ghost_rule(I, side, real(jj), axp, sxp, axT, sxT);
+            real_node = false;
+        }
+    }
+    // points beyond the one-node ring of the lattice are never read by a
+    // stencil; clamping keeps their loads in bounds for tiny lattices
+    sx = ii < 0 ? 0 : (ii >= nx ? nx - 1 : ii);
+    sy = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
+    aphi = ayp + syp * axp;
+    sphi = syp * sxp;
+    aT = ayT + syT * axT;
+    sT = syT * sxT;
+    return real_node;
+}
+
+// Fills one patch entry from global memory (ring entries and tile entries whose
+// node lies outside the lattice).
+template <typename real, int TX, int TY>
+__device__ inline void fill_entry(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int q,
+                                  int gx, int gy)
+{
+    int sx, sy;
+    real aphi, sphi, aT, sT;
+    const bool rn = resolve(I, gx, gy, sx, sy, aphi, sphi, aT, sT);
+    const long long P = I.plane;
+    const long long idx = (long long)sy * I.pitch + sx;
+    real sf = 0, sh = 0, hk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        sf += A[(kF + k) * P + idx];
+        hk[k] = A[(kH + k) * P + idx];
+        sh += hk[k];
+    }
+    const real dphi = aphi + sphi * sf;
+    S.phi[q] = dphi;
+    S.T[q] = aT + sT * sh;
+    S.irc[q] = real(1) / (I.rcp_a + I.rcp_b * (I.phi0 + dphi));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S.h[k][q] = rn ? hk[k] : real(0);
+}
+
+// Loads the work-item's own node and fills the patch.  Returns whether the
+// work-item's node lies in the lattice.
+template <typename real, int TX, int TY>
+__device__ inline bool load_patch(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int x0,
+                                  int y0, real (&f)[9], real (&g)[9], real (&h)[9])
+{
+    using PT = Patch<real, TX, TY>;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gi = x0 + lx, gj = y0 + ly;
+    const bool inside = gi < I.nx && gj < I.ny;
+    const int c = (ly + 1) * PT::PX + (lx + 1);
+    if (inside) {
+        const long long P = I.plane;
+        const long long idx = (long long)gj * I.pitch + gi;
+        real sf = 0, sh = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = A[(kF + k) * P + idx];
+            h[k] = A[(kH + k) * P + idx];
+            g[k] = A[(kG + k) * P + idx];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sf += f[k];
+            sh += h[k];
+        }
+        S.phi[c] = sf;
+        S.T[c] = sh;
+        S.irc[c] = real(1) / (I.rcp_a + I.rcp_b * (I.phi0 + sf));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S.h[k][c] = h[k];
+    } else {
+        fill_entry<real, TX, TY>(I, A, S, c, gi, gj);
+    }
+    for (int q = tid; q < PT::NRING; q += TX * TY) {
+        int hx, hy;
+        if (q < PT::PX) { hx = q - 1; hy = -1; }
+        else if (q < 2 * PT::PX) { hx = q - PT::PX - 1; hy = TY; }
+        else {
+            const int r = q - 2 * PT::PX;
+            hx = r < TY ? -1 : TX;
+            hy = r < TY ? r : r - TY;
+        }
+        fill_entry<real, TX, TY>(I, A, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
+    }
+    __syncthreads();
+    return inside;
+}
+
+template <typename real>
+struct Macro {
+    real dphi, phi, theta;
+    real gpx, gpy, gtx, gty;
+    real rho, ux, uy, p, Fx, Fy, grx, gry, irho;
+};
+
+// Pass-1 quantities of one node from the patch and its own g_i.
+template <typename real, int PX>
+__device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __restrict__ sphi,
+                                          const real* __restrict__ sT, int c, const real (&g)[9])
+{
+    Macro<real> m;
+    const real pc = sphi[c];
+    const real pE = sphi[c + 1], pW = sphi[c - 1], pN = sphi[c + PX], pS = sphi[c - PX];
+    const real pNE = sphi[c + PX + 1], pNW = sphi[c + PX - 1], pSW = sphi[c - PX - 1], pSE = sphi[c - PX + 1];
+    const real tE = sT[c + 1], tW = sT[c - 1], tN = sT[c + PX], tS = sT[c - PX];
+    const real tNE = sT[c + PX + 1], tNW = sT[c + PX - 1], tSW = sT[c - PX - 1], tSE = sT[c - PX + 1];
+    const real third = real(1.0 / 3.0), twelfth = real(1.0 / 12.0);
+    // grad psi = 3 sum w_i c_i psi(x + c_i); lap psi = 6 sum_{i>0} w_i (psi(x + c_i) - psi(x))
+    m.gpx = third * (pE - pW) + twelfth * ((pNE - pNW) + (pSE - pSW));
+    m.gpy = third * (pN - pS) + twelfth * ((pNE + pNW) - (pSW + pSE));
+    const real lap = real(2.0 / 3.0) * ((pE + pW) + (pN + pS) - real(4) * pc)
+                   + real(1.0 / 6.0) * ((pNE + pNW) + (pSW + pSE) - real(4) * pc);
+    m.gtx = third * (tE - tW) + twelfth * ((tNE - tNW) + (tSE - tSW));
+    m.gty = third * (tN - tS) + twelfth * ((tNE + tNW) - (tSW + tSE));
+
+    m.dphi = pc;
+    m.phi = I.phi0 + pc;
+    m.theta = sT[c];
+    const real phi = m.phi;
+    m.rho = I.rho_a + I.rho_b * phi;
+    m.irho = real(1) / m.rho;
+    m.grx = I.rho_b * m.gpx;
+    m.gry = I.rho_b * m.gpy;
+    // chemical potential phi^3 - phi - W^2 lap phi, written so that phi - 1 is exact near phi0 = 1
+    const real pm1 = (I.phi0 - real(1)) + pc;
+    const real mu_phi = pm1 * (phi + real(1)) * phi - I.W2 * lap;
+    // sigma(T) and grad sigma = sigma'(T) grad T
+    const real dT = I.dTref + m.theta;
+    const real sig = I.sigma_ref + dT * (I.sigma_T + real(0.5) * I.sigma_TT * dT);
+    const real dsig = I.sigma_T + I.sigma_TT * dT;
+    const real gsx = dsig * m.gtx, gsy = dsig * m.gty;
+    // F_s = 3 sqrt2 W/4 [|grad phi|^2 grad sigma - (grad sigma . grad phi) grad phi + sigma/W^2 mu_phi grad phi]
+    const real g2 = m.gpx * m.gpx + m.gpy * m.gpy;
+    const real sdp = gsx * m.gpx + gsy * m.gpy;
+    const real cap = sig * I.inv_W2 * mu_phi;
+    m.Fx = I.pref * (g2 * gsx + (cap - sdp) * m.gpx) + I.Gx;
+    m.Fy = I.pref * (g2 * gsy + (cap - sdp) * m.gpy) + I.Gy;
+    // rho u = sum c_i g_i + F/2
+    const real mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const real my = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    m.ux = (mx + real(0.5) * m.Fx) * m.irho;
+    m.uy = (my + real(0.5) * m.Fy) * m.irho;
+    // p = c_s^2/(1 - w_0) [sum_{i>0} g_i + u.grad rho/2 + rho s_0(u)], s_0 = -w_0 |u|^2 / (2 c_s^2)
+    const real sg = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+    const real uu = m.ux * m.ux + m.uy * m.uy;
+    m.p = real(0.6) * (sg + real(0.5) * (m.ux * m.grx + m.uy * m.gry) - real(2.0 / 3.0) * m.rho * uu);
+    return m;
+}
+
+// Streaming destination of direction k from (gi, gj): returns true and the
+// destination index if it stays in the lattice (after periodic wrap);
+// otherwise returns false and the side whose rule applies.
+template <typename real>
+__device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, long long& idx, int& side)
+{
+    int ti = gi + cx(k), tj = gj + cy(k);
+    bool ox = false, oy = false;
+    int sxs = 0, sys = 2;
+    if (ti < 0) { sxs = 0; if (I.bc[0] == BC_PERIODIC) ti += I.nx; else ox = true; }
+    else if (ti >= I.nx) { sxs = 1; if (I.bc[1] == BC_PERIODIC) ti -= I.nx; else ox = true; }
+    if (tj < 0) { sys = 2; if (I.bc[2] == BC_PERIODIC) tj += I.ny; else oy = true; }
+    else if (tj >= I.ny) { sys = 3; if (I.bc[3] == BC_PERIODIC) tj -= I.ny; else oy = true; }
+    if (!ox && !oy) {
+        idx = (long long)tj * I.pitch + ti;
+        return true;
+    }
+    if (ox && oy) {
+        const int bx = I.bc[sxs], by = I.bc[sys];
+        const int px = (bx == BC_WALL_T || bx == BC_WALL_ADIABATIC) ? 2 : (bx == BC_INLET ? 1 : 0);
+        const int py = (by == BC_WALL_T || by == BC_WALL_ADIABATIC) ? 2 : (by == BC_INLET ? 1 : 0);
+        side = px > py ? sxs : sys;
+    } else {
+        side = ox ? sxs : sys;
+    }
+    return false;
+}
+
+template <typename real, int TX, int TY>
+__device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
+{
+    using PT = Patch<real, TX, TY>;
+    constexpr int PX = PT::PX;
+    const real* __restrict__ A = I.pop[src];
+    real* __restrict__ B = I.pop[src ^ 1];
+    real f[9], g[9], h[9];
+    const bool inside = load_patch<real, TX, TY>(I, A, S, x0, y0, f, g, h);
+    if (!inside) return;
+    const int tid = threadIdx.x;
+    const int gi = x0 + tid % TX, gj = y0 + tid / TX;
+    const int c = (tid / TX + 1) * PX + (tid % TX + 1);
+    const long long P = I.plane;
+    const long long own = (long long)gj * I.pitch + gi;
+    const real jpx = I.jprev[own], jpy = I.jprev[P + own];
+
+    const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
+    const real phi = m.phi, ux = m.ux, uy = m.uy;
+    const real mu = I.mu_a + I.mu_b * phi;
+    const real lam = I.lam_a + I.lam_b * phi;
+    const real rcp = I.rcp_a + I.rcp_b * phi;
+    // mu = rho c_s^2 (tau_g - 1/2), lambda = c_s^2 (tau_h - 1/2)
+    const real inv_tau_g = m.rho / (real(0.5) * m.rho + real(3) * mu);
+    const real fac_g = real(1) - real(0.5) * inv_tau_g;
+    const real tau_h = real(0.5) + real(3) * lam;
+    const real inv_tau_h = real(1) / tau_h;
+
+    // time derivative of phi u by the first-order Euler scheme; store phi u
+    const real jx = phi * ux, jy = phi * uy;
+    const real djx = jx - jpx, djy = jy - jpy;
+    I.jprev[own] = jx;
+    I.jprev[P + own] = jy;
+
+    // Allen-Cahn source: unit normal from v = sum c_i (f_i - f_i^eq) + dt(phi u)/2, n = -v/|v|
+    real nxv = 0, nyv = 0;
+    if (I.grad_mode == 0) {
+        const real vx = ((f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7])) - jx + real(0.5) * djx;
+        const real vy = ((f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8])) - jy + real(0.5) * djy;
+        const real vn2 = vx * vx + vy * vy;
+        if (vn2 > real(0)) {
+            const real iv = real(1) / sqrt(vn2);
+            nxv = -vx * iv;
+            nyv = -vy * iv;
+        }
+    } else {
+        const real gn2 = m.gpx * m.gpx + m.gpy * m.gpy;
+        if (gn2 > real(0)) {
+            const real ig = real(1) / sqrt(gn2);
+            nxv = m.gpx * ig;
+            nyv = m.gpy * ig;
+        }
+    }
+    const real pm1 = (I.phi0 - real(1)) + m.dphi;
+    const real lamc = -pm1 * (phi + real(1)) * I.inv_s2W;  // (1 - phi^2)/(sqrt2 W)
+    const real ax = real(3) * djx + lamc * nxv;               // R_i = w_i c_i . (3 dt(phi u) + lamc n)
+    const real ay = real(3) * djy + lamc * nyv;
+
+    // thermal source: grad T from the first moment of h (or the stencil), Fhat = -rho c_p u . grad T
+    real tgx, tgy;
+    if (I.grad_mode == 0) {
+        const real hx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+        const real hy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+        tgx = real(-3) * hx * inv_tau_h;
+        tgy = real(-3) * hy * inv_tau_h;
+    } else {
+        tgx = m.gtx;
+        tgy = m.gty;
+    }
+    const real Fhat = -rcp * (ux * tgx + uy * tgy);
+
+    const real uu = ux * ux + uy * uy;
+    const real p3 = real(3) * m.p;
+    const real theta = m.theta;
+
+    real fs[9], gs[9], hs[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const real w = wgt<real>(k);
+        const real cu = real(cx(k)) * ux + real(cy(k)) * uy;
+        // Eq. 14: f* = f - (f - f^eq)/tau_phi + (1 - 1/(2 tau_phi)) R_i
+        const real feq = w * (m.dphi + real(3) * phi * cu);
+        const real Ri = w * (real(cx(k)) * ax + real(cy(k)) * ay);
+        fs[k] = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
+        // NS LBE: g^eq = 3 p (w_i - delta_i0) + rho s_i(u); G_i = w_i [3 c_i.F + 3 (c_i.u)(c_i.grad rho)]
+        const real si = w * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
+        const real geq = (k == 0 ? p3 * (w - real(1)) : p3 * w) + m.rho * si;
+        const real cF = real(cx(k)) * m.Fx + real(cy(k)) * m.Fy;
+        const real cg = real(cx(k)) * m.grx + real(cy(k)) * m.gry;
+        const real Gi = w * real(3) * (cF + cu * cg);
+        gs[k] = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
+        // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat
+        hs[k] = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
+    }
+
+    // push streaming; thermal update at the destination y = x + c_i:
+    // h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        long long di;
+        int side;
+        if (dest(I, gi, gj, k, di, side)) {
+            const int cd = c + cy(k) * PX + cx(k);
+            B[(kF + k) * P + di] = fs[k];
+            B[(kG + k) * P + di] = gs[k];
+            const real hold = S.h[k][cd];
+            B[(kH + k) * P + di] = hold + (hs[k] - hold) * S.irc[cd];
+        } else {
+            const int kb = opp(k);
+            const int bc = I.bc[side];
+            const real w = wgt<real>(k);
+            const real s = side < 2 ? real(gj) + real(0.5) * real(cy(k)) : real(gi) + real(0.5) * real(cx(k));
+            real fb, gb, hb;
+            if (bc == BC_WALL_T || bc == BC_WALL_ADIABATIC) {
+                // halfway bounce-back; anti-bounce-back for a Dirichlet temperature
+                fb = fs[k];
+                gb = gs[k];
+                hb = bc == BC_WALL_T ? -hs[k] + real(2) * w * wall_T(I, side, s) : hs[k];
+            } else if (bc == BC_INLET) {
+                // anti-bounce-back for phi and T, moving-wall bounce-back for u
+                const real H = side < 2 ? real(I.ny) : real(I.nx);
+                const real sp = s + real(0.5);
+                const real un = real(6) * I.u_in * sp * (H - sp) / (H * H);
+                const real uix = side == 0 ? un : (side == 1 ? -un : real(0));
+                const real uiy = side == 2 ? un : (side == 3 ? -un : real(0));
+                fb = -fs[k] + real(2) * w * I.phi_in_d;
+                gb = gs[k] - real(6) * w * m.rho * (real(cx(k)) * uix + real(cy(k)) * uiy);
+                hb = -hs[k] + real(2) * w * I.T_in_d;
+            } else {  // outlet: anti-bounce-back at p = 0 with the node's own u, phi, T
+                const real cu = real(cx(k)) * ux + real(cy(k)) * uy;
+                fb = -fs[k] + real(2) * w * m.dphi;
+                gb = -gs[k] + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * uu);
+                hb = -hs[k] + real(2) * w * theta;
+            }
+            B[(kF + kb) * P + own] = fb;
+            B[(kG + kb) * P + own] = gb;
+            const real hold = S.h[kb][c];
+            B[(kH + kb) * P + own] = hold + (hb - hold) * S.irc[c];
+        }
+    }
+}
+
+// Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
+// the 8 XCDs; renumbering them so each XCD gets a contiguous block of logical
+// ids keeps vertically adjacent tiles (which share ring rows) in one L2.
+__device__ inline void my_tiles(int ntiles, int& t0, int& t1)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    const int xcd = b % 8, per = G / 8, rem = G % 8;
+    const int L = xcd * per + (xcd < rem ? xcd : rem) + b / 8;
+    t0 = (int)((long long)L * ntiles / G);
+    t1 = (int)((long long)(L + 1) * ntiles / G);
+}
+
+template <typename real, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                  int ntiles, int src)
+{
+    __shared__ Patch<real, TX, TY> S;
+    int t0, t1;
+    my_tiles(ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const Tile tl = tiles[t];
+        tile_step<real, TX, TY>(insts[tl.inst], tl.x0, tl.y0, src, S);
+        if (t + 1 < t1) __syncthreads();
+    }
+}
+
+template <typename real, typename out_t>
+__device__ inline void put(void* p, long long i, real v)
+{
+    if (p) static_cast<out_t*>(p)[i] = static_cast<out_t>(v);
+}
+
+template <typename real, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                    int ntiles, int src, void* ophi, void* oux, void* ouy, void* oT,
+                                                    void* op, int out_f32, int jprev_out)
+{
+    __shared__ Patch<real, TX, TY> S;
+    int t0, t1;
+    my_tiles(ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const Tile tl = tiles[t];
+        const Inst<real>& I = insts[tl.inst];
+        real f[9], g[9], h[9];
+        const bool inside = load_patch<real, TX, TY>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+        if (inside) {
+            const int tid = threadIdx.x;
+            const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
+            const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
+            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX>(I, S.phi, S.T, c, g);
+            if (jprev_out) {
+                const long long own = (long long)gj * I.pitch + gi;
+                I.jprev[own] = m.phi * m.ux;
+                I.jprev[I.plane + own] = m.phi * m.uy;
+            } else {
+                const long long o = (long long)gj * I.nx + gi;
+                const double phi = (double)I.phi0 + (double)m.dphi;
+                const double T = (double)I.T0 + (double)m.theta;
+                if (out_f32) {
+                    put<double, float>(ophi, o, phi);
+                    put<real, float>(oux, o, m.ux);
+                    put<real, float>(ouy, o, m.uy);
+                    put<double, float>(oT, o, T);
+                    put<real, float>(op, o, m.p);
+                } else {
+                    put<double, double>(ophi, o, phi);
+                    put<real, double>(oux, o, m.ux);
+                    put<real, double>(ouy, o, m.uy);
+                    put<double, double>(oT, o, T);
+                    put<real, double>(op, o, m.p);
+                }
+            }
+        }
+        if (t + 1 < t1) __syncthreads();
+    }
+}
+
+// Equilibrium populations for given fields (p = 0): f_i = w_i phi (1 + 3 c_i.u),
+// g_i = rho s_i(u), h_i = w_i T, stored as deviations.  Computed in FP64.
+template <typename real>
+__global__ void k_init(const Inst<real>* __restrict__ insts, const double* __restrict__ staged, double phi0,
+                       double T0, double rho_a, double rho_b, int src)
+{
+    const Inst<real>& I = insts[0];
+    const long long n = (long long)I.nx * I.ny;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int i = (int)(x % I.nx), j = (int)(x / I.nx);
+    const double phi = staged[x], ux = staged[n + x], uy = staged[2 * n + x], T = staged[3 * n + x];
+    const double rho = rho_a + rho_b * phi;
+    const double uu = ux * ux + uy * uy;
+    real* __restrict__ A = I.pop[src];
+    const long long P = I.plane, idx = (long long)j * I.pitch + i;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double w = wgt<double>(k);
+        const double cu = cx(k) * ux + cy(k) * uy;
+        A[(kF + k) * P + idx] = (real)(w * ((phi - phi0) + 3.0 * phi * cu));
+        A[(kG + k) * P + idx] = (real)(rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        A[(kH + k) * P + idx] = (real)(w * (T - T0));
+    }
+}
+
+// ---- FP64 diagnostics ----
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename real, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                  int ntiles, int src, DiagArgs a, double rcp_a, double rcp_b,
+                                                  double* __restrict__ partials)
+{
+    __shared__ Patch<real, TX, TY> S;
+    __shared__ double red[(TX * TY) / 64][D_COUNT];
+    double acc[D_COUNT];
+#pragma unroll
+    for (int q = 0; q < D_COUNT; ++q) acc[q] = 0.0;
+    int t0, t1;
+    my_tiles(ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const Tile tl = tiles[t];
+        const Inst<real>& I = insts[tl.inst];
+        real f[9], g[9], h[9];
+        const bool inside = load_patch<real, TX, TY>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+        if (inside) {
+            const int tid = threadIdx.x;
+            const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
+            const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
+            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX>(I, S.phi, S.T, c, g);
+            const double phi = (double)I.phi0 + (double)m.dphi;
+            const double T = (double)I.T0 + (double)m.theta;
+            const double ux = m.ux, uy = m.uy, p = m.p;
+            if (!isfinite(phi) || !isfinite(T) || !isfinite(ux) || !isfinite(uy) || !isfinite(p)) {
+                acc[D_NONFIN] += 1.0;
+            } else {
+                acc[D_MASS] += phi;
+                acc[D_VOL] += 0.5 * (1.0 - phi);
+                acc[D_HEAT] += (rcp_a + rcp_b * phi) * T;
+                acc[D_MAXU] = fmax(acc[D_MAXU], sqrt(ux * ux + uy * uy));
+                if (phi < 0.0) {
+                    acc[D_NNEG] += 1.0;
+                    acc[D_SNEG] += phi;
+                    acc[D_SUY] += phi * uy;
+                    acc[D_SUX] += phi * ux;
+                    acc[D_SX] += phi * gi;
+                    acc[D_SY] += phi * gj;
+                    if (a.n_bubbles > 0) {
+                        int best = 0;
+                        double bd = 0.0;
+                        for (int b = 0; b < a.n_bubbles; ++b) {
+                            const double dx = gi - a.bx[b], dy = gj - a.by[b];
+                            const double d2 = dx * dx + dy * dy;
+                            if (b == 0 || d2 < bd) { bd = d2; best = b; }
+                        }
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            if (b == best) {
+                                acc[D_BUB + 5 * b + 0] += phi;
+                                acc[D_BUB + 5 * b + 1] += phi * gi;
+                                acc[D_BUB + 5 * b + 2] += phi * gj;
+                                acc[D_BUB + 5 * b + 3] += phi * ux;
+                                acc[D_BUB + 5 * b + 4] += phi * uy;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int q = 0; q < D_COUNT; ++q) {
+        const double v = q == D_MAXU ? wave_max(acc[q]) : wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < D_COUNT) {
+        const int q = threadIdx.x;
+        double v = red[0][q];
+        for (int w = 1; w < (TX * TY) / 64; ++w) v = q == D_MAXU ? fmax(v, red[w][q]) : v + red[w][q];
+        partials[(long long)blockIdx.x * D_COUNT + q] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partials, int nblocks,
+                                                    double* __restrict__ result)
+{
+    __shared__ double red[4][D_COUNT];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int q = 0; q < D_COUNT; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) {
+            const double x = partials[(long long)b * D_COUNT + q];
+            v = q == D_MAXU ? fmax(v, x) : v + x;
+        }
+        v = q == D_MAXU ? wave_max(v) : wave_sum(v);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < D_COUNT) {
+        const int q = threadIdx.x;
+        double v = red[0][q];
+        for (int w = 1; w < 4; ++w) v = q == D_MAXU ? fmax(v, red[w][q]) : v + red[w][q];
+        result[q] = v;
+    }
+}
+
+// ---- launchers ----
+
+template <typename real, int TX, int TY>
+static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, hipStream_t s)
+{
+    const int G = grid > 0 ? grid : ntiles;
+    hipLaunchKernelGGL((k_step<real, TX, TY>), dim3(G), dim3(TX * TY), 0, s, static_cast<const Inst<real>*>(insts),
+                       tiles, ntiles, src);
+    return hipGetLastError();
+}
+
+template <typename real, int TX, int TY>
+static hipError_t fields_t(const void* insts, const Tile* tiles, int ntiles, int src, void* phi, void* ux, void* uy,
+                           void* T, void* p, int out_f32, int jprev_out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fields<real, TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s,
+                       static_cast<const Inst<real>*>(insts), tiles, ntiles, src, phi, ux, uy, T, p, out_f32,
+                       jprev_out);
+    return hipGetLastError();
+}
+
+template <typename real, int TX, int TY>
+static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int src, const DiagArgs& a,
+                         double rcp_a, double rcp_b, double* partials, double* result, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_diag<real, TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s,
+                       static_cast<const Inst<real>*>(insts), tiles, ntiles, src, a, rcp_a, rcp_b, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, partials, ntiles, result);
+    return hipGetLastError();
+}
+
+#define LBM_TILE_SWITCH(TILE, CALL)                  \
+    switch (TILE) {                                  \
+    case 0: return CALL(64, 4);                      \
+    case 1: return CALL(128, 2);                     \
+    case 2: return CALL(32, 8);                      \
+    case 3: return CALL(64, 8);                      \
+    case 4: return CALL(256, 1);                     \
+    case 5: return CALL(128, 4);                     \
+    default: return hipErrorInvalidValue;            \
+    }
+
+hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
+                       hipStream_t s)
+{
+#define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, s)
+#define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, s)
+    if (prec == 0) { LBM_TILE_SWITCH(tile, STEP64) }
+    LBM_TILE_SWITCH(tile, STEP32)
+#undef STEP64
+#undef STEP32
+}
+
+hipError_t launch_fields(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src, void* phi,
+                         void* ux, void* uy, void* T, void* p, int out_f32, int jprev_out, hipStream_t s)
+{
+#define F64(a, b) fields_t<double, a, b>(insts, tiles, ntiles, src, phi, ux, uy, T, p, out_f32, jprev_out, s)
+#define F32(a, b) fields_t<float, a, b>(insts, tiles, ntiles, src, phi, ux, uy, T, p, out_f32, jprev_out, s)
+    if (prec == 0) { LBM_TILE_SWITCH(tile, F64) }
+    LBM_TILE_SWITCH(tile, F32)
+#undef F64
+#undef F32
+}
+
+hipError_t launch_init(int prec, const void* inst_dev, long long n_nodes, const double* staged, const InitArgs& a,
+                       int src, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n_nodes + 255) / 256));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, s, static_cast<const Inst<double>*>(inst_dev), staged,
+                           a.phi0, a.T0, a.rho_a, a.rho_b, src);
+    else
+        hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, s, static_cast<const Inst<float>*>(inst_dev), staged,
+                           a.phi0, a.T0, a.rho_a, a.rho_b, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src,
+                       const DiagArgs& a, double* partials, double* result, hipStream_t s)
+{
+#define D64(x, y) diag_t<double, x, y>(insts, tiles, ntiles, src, a, a.rcp_a, a.rcp_b, partials, result, s)
+#define D32(x, y) diag_t<float, x, y>(insts, tiles, ntiles, src, a, a.rcp_a, a.rcp_b, partials, result, s)
+    if (prec == 0) { LBM_TILE_SWITCH(tile, D64) }
+    LBM_TILE_SWITCH(tile, D32)
+#undef D64
+#undef D32
+}
+
+}  // namespace lbm

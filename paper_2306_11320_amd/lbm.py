@@ -1,0 +1,327 @@
+"""ctypes binding of the C ABI in ``include/lbm.h`` (argument marshalling only).
+
+Every step of the lattice Boltzmann update runs in the HIP kernels of
+``liblbm_hip.so``; this module allocates the device workspace and the stream
+with PyTorch and passes raw pointers.  It fails loudly if the library has not
+been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
+ABI_VERSION = 1
+
+LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32_DEV = 0, 1
+OUT_F64, OUT_F32 = 0, 1
+
+EXPORTED = [
+    "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_diagnostics", "lbm_destroy",
+    "lbm_last_error", "lbm_get_state", "lbm_set_state", "lbm_checkpoint_bytes", "lbm_checkpoint_save",
+    "lbm_checkpoint_load", "lbm_workspace_bytes_batch", "lbm_init_batch", "lbm_instances",
+    "lbm_fields_instance", "lbm_diagnostics_instance", "lbm_tile_count", "lbm_tile_shape", "lbm_set_tile",
+    "lbm_get_tile", "lbm_set_graph_steps", "lbm_set_grid", "lbm_bytes_per_update",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("nx", C.c_uint32), ("ny", C.c_uint32), ("precision", C.c_uint32),
+        ("bc", C.c_uint32 * 4), ("grad_mode", C.c_uint32), ("n_bubbles", C.c_uint32),
+        ("rho_l", C.c_double), ("rho_h", C.c_double), ("mu_l", C.c_double), ("mu_h", C.c_double),
+        ("lambda_l", C.c_double), ("lambda_h", C.c_double), ("rhocp_l", C.c_double), ("rhocp_h", C.c_double),
+        ("sigma_ref", C.c_double), ("sigma_T", C.c_double), ("sigma_TT", C.c_double), ("T_ref", C.c_double),
+        ("W", C.c_double), ("mobility", C.c_double), ("Gx", C.c_double), ("Gy", C.c_double),
+        ("Tw_mean", C.c_double * 4), ("Tw_amp", C.c_double * 4), ("Tw_k", C.c_double * 4),
+        ("Tw_slope", C.c_double * 4),
+        ("u_in_mean", C.c_double), ("phi_in", C.c_double), ("T_in", C.c_double),
+        ("phi0_dev", C.c_double), ("T0_dev", C.c_double),
+        ("bubble_x", C.c_double * 4), ("bubble_y", C.c_double * 4),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("mass_phi", C.c_double), ("vol_light", C.c_double), ("heat", C.c_double),
+        ("sum_neg", C.c_double), ("u_r", C.c_double), ("ux_r", C.c_double), ("xc", C.c_double),
+        ("yc", C.c_double), ("max_u", C.c_double), ("n_nonfinite", C.c_int64), ("n_neg", C.c_int64),
+        ("bub_x", C.c_double * 4), ("bub_y", C.c_double * 4), ("bub_ux", C.c_double * 4),
+        ("bub_uy", C.c_double * 4), ("bub_sum", C.c_double * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, C.Array) else v
+        return out
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with "
+                                   "`python -m paper_2306_11320_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+            L.lbm_workspace_bytes.restype = C.c_size_t
+            L.lbm_workspace_bytes.argtypes = [C.POINTER(Params)]
+            L.lbm_workspace_bytes_batch.restype = C.c_size_t
+            L.lbm_workspace_bytes_batch.argtypes = [C.POINTER(Params), ip]
+            L.lbm_init.argtypes = [C.POINTER(Params), dp, dp, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+            L.lbm_init_batch.argtypes = [ip, C.POINTER(Params), C.POINTER(dp), C.POINTER(dp), C.POINTER(dp),
+                                         C.POINTER(dp), vp, C.c_size_t, vp, C.POINTER(vp)]
+            L.lbm_step.argtypes = [vp, C.c_int64]
+            L.lbm_fields.argtypes = [vp, vp, vp, vp, vp, vp, ip]
+            L.lbm_fields_instance.argtypes = [vp, ip, vp, vp, vp, vp, vp, ip]
+            L.lbm_diagnostics.argtypes = [vp, C.POINTER(Diag)]
+            L.lbm_diagnostics_instance.argtypes = [vp, ip, C.POINTER(Diag)]
+            L.lbm_destroy.argtypes = [vp]
+            L.lbm_last_error.restype = C.c_char_p
+            L.lbm_get_state.argtypes = [vp, ip, dp, dp, dp, dp, C.POINTER(C.c_int64)]
+            L.lbm_set_state.argtypes = [vp, ip, dp, dp, dp, dp, C.c_int64]
+            L.lbm_checkpoint_bytes.restype = C.c_size_t
+            L.lbm_checkpoint_bytes.argtypes = [vp]
+            L.lbm_checkpoint_save.argtypes = [vp, vp, C.c_size_t]
+            L.lbm_checkpoint_load.argtypes = [vp, vp, C.c_size_t]
+            L.lbm_instances.argtypes = [vp]
+            L.lbm_tile_shape.argtypes = [ip, C.POINTER(ip), C.POINTER(ip)]
+            L.lbm_set_tile.argtypes = [vp, ip]
+            L.lbm_get_tile.argtypes = [vp]
+            L.lbm_set_graph_steps.argtypes = [vp, ip]
+            L.lbm_set_grid.argtypes = [vp, ip]
+            L.lbm_bytes_per_update.restype = C.c_size_t
+            L.lbm_bytes_per_update.argtypes = [ip]
+            _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+    return rc
+
+
+def make_params(cfg: dict, precision: int = FP64) -> Params:
+    """Marshal a workload parameter dict (``paper_2306_11320_amd.workloads``)."""
+    p = Params()
+    p.abi_version = ABI_VERSION
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.precision = int(precision)
+    for s in range(4):
+        p.bc[s] = int(cfg["bc"][s])
+        p.Tw_mean[s] = float(cfg.get("tw_mean", [0.0] * 4)[s])
+        p.Tw_amp[s] = float(cfg.get("tw_amp", [0.0] * 4)[s])
+        p.Tw_k[s] = float(cfg.get("tw_k", [0.0] * 4)[s])
+        p.Tw_slope[s] = float(cfg.get("tw_slope", [0.0] * 4)[s])
+    p.grad_mode = int(cfg.get("grad_mode", 0))
+    bx, by = list(cfg.get("bubbles_x", [])), list(cfg.get("bubbles_y", []))
+    p.n_bubbles = len(bx)
+    for b in range(len(bx)):
+        p.bubble_x[b], p.bubble_y[b] = float(bx[b]), float(by[b])
+    for k in ("rho_l", "rho_h", "mu_l", "mu_h", "lambda_l", "lambda_h", "rhocp_l", "rhocp_h", "sigma_ref",
+              "sigma_T", "sigma_TT", "T_ref", "W", "mobility", "Gx", "Gy", "u_in_mean", "phi_in", "T_in"):
+        setattr(p, k, float(cfg.get(k, 0.0)))
+    if precision == FP32_DEV:
+        # rest state of the deviation storage: host phase and reference temperature
+        p.phi0_dev = float(cfg.get("phi0_dev") or 1.0)
+        p.T0_dev = float(cfg["T0_dev"]) if cfg.get("T0_dev") else float(cfg.get("T_ref", 0.0))
+    else:
+        p.phi0_dev = float(cfg.get("phi0_dev", 0.0))
+        p.T0_dev = float(cfg.get("T0_dev", 0.0))
+    return p
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _fields_arrays(f0: dict, n: int):
+    arrs = [np.ascontiguousarray(f0[k], dtype=np.float64).reshape(-1) for k in ("phi", "ux", "uy", "T")]
+    for a in arrs:
+        if a.size != n:
+            raise ValueError("initial field has the wrong size")
+    return arrs
+
+
+class Lattice:
+    """One or more lattices advanced together on one HIP stream.
+
+    ``Lattice(cfg, fields0)`` holds one lattice; ``Lattice.batch([(cfg, f0),
+    ...])`` holds many (possibly of different sizes) stepped by one launch.
+    """
+
+    def __init__(self, cfg: dict, fields0: dict, precision: int = FP64, device: str = "cuda:0", stream=None):
+        self._init([(cfg, fields0)], precision, device, stream)
+
+    @classmethod
+    def batch(cls, items, precision: int = FP32_DEV, device: str = "cuda:0", stream=None) -> "Lattice":
+        obj = cls.__new__(cls)
+        obj._init(list(items), precision, device, stream)
+        return obj
+
+    def _init(self, items, precision, device, stream):
+        import torch
+        self.L = lib()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = int(precision)
+        self.cfgs = [c for c, _ in items]
+        self.shapes = [(int(c["ny"]), int(c["nx"])) for c in self.cfgs]
+        n = len(items)
+        ps = (Params * n)(*[make_params(c, precision) for c in self.cfgs])
+        self._params = ps
+        ws = self.L.lbm_workspace_bytes_batch(ps, n)
+        if ws == 0:
+            raise LbmError(LBM_EINVAL, self.L.lbm_last_error().decode() or "invalid parameters")
+        self.ws_bytes = ws
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        keep = [_fields_arrays(f, ny * nx) for (_, f), (ny, nx) in zip(items, self.shapes)]
+        self._keep = keep
+        DP = C.POINTER(C.c_double)
+        cols = [(DP * n)(*[_dp(k[q]) for k in keep]) for q in range(4)]
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.L.lbm_init_batch(n, ps, cols[0], cols[1], cols[2], cols[3],
+                                       C.c_void_p(self.workspace.data_ptr()), C.c_size_t(ws),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        _check(rc)
+        self._h = h
+        self.n = n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.L.lbm_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    # ---- the four calls of the boundary ----
+    def step(self, n: int = 1) -> None:
+        _check(self.L.lbm_step(self._h, int(n)))
+
+    def fields(self, instance: int = 0, out: str = "f64", to_host: bool = True) -> dict:
+        torch = self.torch
+        ny, nx = self.shapes[instance]
+        dt = torch.float64 if out == "f64" else torch.float32
+        bufs = {k: torch.empty((ny, nx), dtype=dt, device=self.device) for k in ("phi", "ux", "uy", "T", "p")}
+        _check(self.L.lbm_fields_instance(self._h, int(instance), *[C.c_void_p(bufs[k].data_ptr())
+                                                                    for k in ("phi", "ux", "uy", "T", "p")],
+                                          OUT_F64 if out == "f64" else OUT_F32))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        if to_host:
+            self.stream.synchronize()
+            return {k: v.cpu().numpy() for k, v in bufs.items()}
+        return bufs
+
+    def diagnostics(self, instance: int = 0, raise_unstable: bool = False) -> dict:
+        d = Diag()
+        rc = self.L.lbm_diagnostics_instance(self._h, int(instance), C.byref(d))
+        if rc == LBM_EUNSTABLE and not raise_unstable:
+            out = d.as_dict()
+            out["unstable"] = True
+            return out
+        _check(rc)
+        out = d.as_dict()
+        out["unstable"] = False
+        return out
+
+    # ---- state transfer ----
+    def get_state(self, instance: int = 0) -> dict:
+        ny, nx = self.shapes[instance]
+        n = nx * ny
+        f, g, h, jp = np.empty(9 * n), np.empty(9 * n), np.empty(9 * n), np.empty(2 * n)
+        st = C.c_int64(0)
+        _check(self.L.lbm_get_state(self._h, int(instance), _dp(f), _dp(g), _dp(h), _dp(jp), C.byref(st)))
+        shp = (9, ny, nx)
+        return {"f": f.reshape(shp), "g": g.reshape(shp), "h": h.reshape(shp), "jprev": jp.reshape(2, ny, nx),
+                "step": st.value}
+
+    def set_state(self, instance: int = 0, f=None, g=None, h=None, jprev=None, step: int = 0) -> None:
+        def conv(a):
+            if a is None:
+                return None, None
+            a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+            return a, _dp(a)
+        keep = [conv(a) for a in (f, g, h, jprev)]
+        _check(self.L.lbm_set_state(self._h, int(instance), *[k[1] for k in keep], int(step)))
+
+    def checkpoint(self) -> bytes:
+        n = self.L.lbm_checkpoint_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        _check(self.L.lbm_checkpoint_save(self._h, buf, C.c_size_t(n)))
+        return buf.raw
+
+    def restore(self, data: bytes) -> None:
+        buf = C.create_string_buffer(data, len(data))
+        _check(self.L.lbm_checkpoint_load(self._h, buf, C.c_size_t(len(data))))
+
+    # ---- launch configuration ----
+    def set_tile(self, tile_id: int) -> None:
+        _check(self.L.lbm_set_tile(self._h, int(tile_id)))
+
+    def tile(self) -> int:
+        return self.L.lbm_get_tile(self._h)
+
+    def set_graph_steps(self, steps: int) -> None:
+        _check(self.L.lbm_set_graph_steps(self._h, int(steps)))
+
+    def set_grid(self, workgroups: int) -> None:
+        _check(self.L.lbm_set_grid(self._h, int(workgroups)))
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+
+def tile_shapes() -> list[tuple[int, int]]:
+    L = lib()
+    out = []
+    for t in range(L.lbm_tile_count()):
+        tx, ty = C.c_int(0), C.c_int(0)
+        _check(L.lbm_tile_shape(t, C.byref(tx), C.byref(ty)))
+        out.append((tx.value, ty.value))
+    return out
+
+
+def bytes_per_update(precision: int) -> int:
+    return int(lib().lbm_bytes_per_update(int(precision)))
+
+
+# names of the C ABI, for callers that prefer the flat interface
+def lbm_init(cfg: dict, fields0: dict, precision: int = FP64, device: str = "cuda:0") -> Lattice:
+    return Lattice(cfg, fields0, precision, device)
+
+
+def lbm_step(lat: Lattice, n: int) -> None:
+    lat.step(n)
+
+
+def lbm_fields(lat: Lattice, instance: int = 0) -> dict:
+    return lat.fields(instance)
+
+
+def lbm_diagnostics(lat: Lattice, instance: int = 0) -> dict:
+    return lat.diagnostics(instance)
