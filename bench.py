@@ -65,6 +65,18 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def prewarm(seconds: float = 0.3):
+    """Brings the GPU out of its idle clocks before anything is timed."""
+    import torch
+    x = torch.ones(1 << 24, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            x.mul_(1.0000001)
+        torch.cuda.synchronize()
+
+
 def time_gpu(items, prec, steps, warmup, tile=None):
     import torch
     from paper_2306_11320_amd import lbm
@@ -121,6 +133,8 @@ def main():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run the plain copy kernel on MIB MiB, 20 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the lattice update is not sharded "
@@ -131,7 +145,26 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        st = torch.cuda.Stream()
+        for _ in range(3):
+            lbm.copy_probe(src, dst, st)
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(20):
+            lbm.copy_probe(src, dst, st)
+        e1.record(st)
+        st.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": ms,
+                          "copy_GBps": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
     items, cfgdesc = make_workload(args.workload)
+    prewarm()
     print(f"[bench] workload {cfgdesc['workload']}: FP32 deviation storage, {args.steps} steps", file=sys.stderr,
           flush=True)
     r32 = time_gpu(items, lbm.FP32_DEV, args.steps, args.warmup, args.tile)
@@ -143,8 +176,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu",
-                       working_set_bytes=2 * bpl // 2 * 2 // 2 * 1 if False else None),
+        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu"),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }

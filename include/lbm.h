@@ -69,7 +69,8 @@ enum {
     LBM_BC_WALL_ADIABATIC = 2, /* halfway bounce-back no-slip wall, zero heat flux */
     LBM_BC_INLET = 3,          /* fully developed inflow 6 u_in s'(H-s')/H^2 along
                                   the inward normal, phi = phi_in, T = T_in (Sec. 4.3) */
-    LBM_BC_OUTLET = 4          /* zero-gradient outflow (Sec. 4.3) */
+    LBM_BC_OUTLET = 4          /* open outflow (Sec. 4.3): anti-bounce-back at
+                                  pressure 0 with the node's own u, phi and T */
 };
 
 enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
@@ -246,6 +247,13 @@ int lbm_set_grid(lbm_ctx* c, int workgroups);
 /* Algorithmic HBM traffic of one lattice update: 27 populations read and
  * written plus (phi u) of the previous level read and written. */
 size_t lbm_bytes_per_update(int precision);
+
+/* Measurement aid, not part of the method: copies `bytes` (a multiple of 16,
+ * both pointers 16-byte aligned, caller-owned device memory) with a plain
+ * vector-copy kernel on `hip_stream`.  Its HBM counters and duration calibrate
+ * the traffic and bandwidth figures reported for the step kernel.
+ * Errors: LBM_EINVAL, LBM_EHIP.  Asynchronous. */
+int lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

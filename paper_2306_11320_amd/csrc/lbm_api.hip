@@ -319,8 +319,15 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
         std::vector<lbm::Tile> tl;
         for (int k = 0; k < n; ++k) {
             const int tx = lbm::kTileTX[t], ty = lbm::kTileTY[t];
-            for (int y = 0; y < lay[k].ny; y += ty)
-                for (int x = 0; x < lay[k].nx; x += tx) tl.push_back(lbm::Tile{k, x, y, 0});
+            const int nx = lay[k].nx, ny = lay[k].ny;
+            const bool px = ps[k].bc[0] == LBM_BC_PERIODIC, py = ps[k].bc[2] == LBM_BC_PERIODIC;
+            for (int y = 0; y < ny; y += ty)
+                for (int x = 0; x < nx; x += tx) {
+                    const bool whole = x + tx <= nx && y + ty <= ny;
+                    const bool inx = px ? nx >= 3 : (x >= 1 && x + tx <= nx - 1);
+                    const bool iny = py ? ny >= 3 : (y >= 1 && y + ty <= ny - 1);
+                    tl.push_back(lbm::Tile{k, x, y, (whole && inx && iny) ? lbm::kTileInterior : 0});
+                }
         }
         c->d_tiles[t] = reinterpret_cast<lbm::Tile*>(c->ws + off_tiles[t]);
         c->ntiles[t] = (int)tl.size();
@@ -728,6 +735,15 @@ int lbm_set_grid(lbm_ctx* c, int workgroups)
     if (workgroups < 0) return fail(LBM_EINVAL, "negative grid");
     drop_graph(c);
     c->grid = workgroups > c->ntiles[c->tile] ? c->ntiles[c->tile] : workgroups;
+    return LBM_OK;
+}
+
+int lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* hip_stream)
+{
+    if (!d_src || !d_dst || bytes == 0 || bytes % 16) return fail(LBM_EINVAL, "copy probe: bad arguments");
+    if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) % 16)
+        return fail(LBM_EINVAL, "copy probe: buffers must be 16-byte aligned");
+    HIP_TRY(lbm::launch_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(hip_stream)));
     return LBM_OK;
 }
 

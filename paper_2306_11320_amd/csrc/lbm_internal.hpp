@@ -35,8 +35,11 @@ struct Inst {
 };
 
 struct Tile {
-    int inst, x0, y0, pad;
+    int inst, x0, y0, flags;
 };
+// The tile is whole and neither it nor its one-node ring crosses a wall, inlet
+// or outlet: streaming and ring loads need at most a periodic wrap.
+constexpr int kTileInterior = 1;
 
 // Sums accumulated by the FP64 diagnostics reduction, per lattice.
 enum DiagSlot {
@@ -77,5 +80,8 @@ hipError_t launch_init(int prec, const void* inst_dev, long long n_nodes, const 
 // into `result` (D_COUNT doubles).
 hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src,
                        const DiagArgs& a, double* partials, double* result, hipStream_t s);
+
+// Plain 16-byte-vector copy of `bytes` (a multiple of 16).
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace lbm

@@ -112,13 +112,23 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
 
 // Fills one patch entry from global memory (ring entries and tile entries whose
 // node lies outside the lattice).
-template <typename real, int TX, int TY>
+// Periodic image of a coordinate at most one period outside [0, n).
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <typename real, int TX, int TY, bool EDGE>
 __device__ inline void fill_entry(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int q,
                                   int gx, int gy)
 {
     int sx, sy;
-    real aphi, sphi, aT, sT;
-    const bool rn = resolve(I, gx, gy, sx, sy, aphi, sphi, aT, sT);
+    real aphi = 0, sphi = 1, aT = 0, sT = 1;
+    bool rn = true;
+    if (EDGE) {
+        rn = resolve(I, gx, gy, sx, sy, aphi, sphi, aT, sT);
+    } else {
+        // tile and ring touch no wall, inlet or outlet: at most a periodic wrap
+        sx = wrap1(gx, I.nx);
+        sy = wrap1(gy, I.ny);
+    }
     const long long P = I.plane;
     const long long idx = (long long)sy * I.pitch + sx;
     real sf = 0, sh = 0, hk[9];
@@ -128,17 +138,18 @@ __device__ inline void fill_entry(const Inst<real>& I, const real* __restrict__ 
         hk[k] = A[(kH + k) * P + idx];
         sh += hk[k];
     }
-    const real dphi = aphi + sphi * sf;
+    const real dphi = EDGE ? aphi + sphi * sf : sf;
     S.phi[q] = dphi;
-    S.T[q] = aT + sT * sh;
+    S.T[q] = EDGE ? aT + sT * sh : sh;
     S.irc[q] = real(1) / (I.rcp_a + I.rcp_b * (I.phi0 + dphi));
 #pragma unroll
     for (int k = 0; k < 9; ++k) S.h[k][q] = rn ? hk[k] : real(0);
+    (void)aphi; (void)sphi; (void)aT; (void)sT;
 }
 
 // Loads the work-item's own node and fills the patch.  Returns whether the
 // work-item's node lies in the lattice.
-template <typename real, int TX, int TY>
+template <typename real, int TX, int TY, bool EDGE>
 __device__ inline bool load_patch(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int x0,
                                   int y0, real (&f)[9], real (&g)[9], real (&h)[9])
 {
@@ -169,7 +180,7 @@ __device__ inline bool load_patch(const Inst<real>& I, const real* __restrict__ 
 #pragma unroll
         for (int k = 0; k < 9; ++k) S.h[k][c] = h[k];
     } else {
-        fill_entry<real, TX, TY>(I, A, S, c, gi, gj);
+        fill_entry<real, TX, TY, EDGE>(I, A, S, c, gi, gj);
     }
     for (int q = tid; q < PT::NRING; q += TX * TY) {
         int hx, hy;
@@ -180,7 +191,7 @@ __device__ inline bool load_patch(const Inst<real>& I, const real* __restrict__ 
             hx = r < TY ? -1 : TX;
             hy = r < TY ? r : r - TY;
         }
-        fill_entry<real, TX, TY>(I, A, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
+        fill_entry<real, TX, TY, EDGE>(I, A, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
     }
     __syncthreads();
     return inside;
@@ -250,9 +261,14 @@ __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __res
 // Streaming destination of direction k from (gi, gj): returns true and the
 // destination index if it stays in the lattice (after periodic wrap);
 // otherwise returns false and the side whose rule applies.
-template <typename real>
+template <typename real, bool EDGE>
 __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, long long& idx, int& side)
 {
+    if (!EDGE) {
+        idx = (long long)wrap1(gj + cy(k), I.ny) * I.pitch + wrap1(gi + cx(k), I.nx);
+        side = 0;
+        return true;
+    }
     int ti = gi + cx(k), tj = gj + cy(k);
     bool ox = false, oy = false;
     int sxs = 0, sys = 2;
@@ -275,7 +291,7 @@ __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, long lon
     return false;
 }
 
-template <typename real, int TX, int TY>
+template <typename real, int TX, int TY, bool EDGE>
 __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
 {
     using PT = Patch<real, TX, TY>;
@@ -283,7 +299,7 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const real* __restrict__ A = I.pop[src];
     real* __restrict__ B = I.pop[src ^ 1];
     real f[9], g[9], h[9];
-    const bool inside = load_patch<real, TX, TY>(I, A, S, x0, y0, f, g, h);
+    const bool inside = load_patch<real, TX, TY, EDGE>(I, A, S, x0, y0, f, g, h);
     if (!inside) return;
     const int tid = threadIdx.x;
     const int gi = x0 + tid % TX, gj = y0 + tid / TX;
@@ -369,6 +385,22 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
         // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat
         hs[k] = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
     }
+    // The rest populations take the balance: f*_0 = f_0 + sum_{i>0} (f_i - f*_i)
+    // equals the BGK value exactly in real arithmetic (sum_i f*_i = sum_i f_i,
+    // sum_i h*_i = sum_i h_i + Fhat), and keeps the stored update mass- and
+    // heat-neutral up to one rounding.  Otherwise each node relaxes toward
+    // w_i times its rounded moment, and identical bulk nodes round alike, so
+    // FP32 storage drifts linearly in time.
+    {
+        real df = 0, dh = 0;
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            df += f[k] - fs[k];
+            dh += h[k] - hs[k];
+        }
+        fs[0] = f[0] + df;
+        hs[0] = (h[0] + Fhat) + dh;
+    }
 
     // push streaming; thermal update at the destination y = x + c_i:
     // h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y)
@@ -376,13 +408,13 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     for (int k = 0; k < 9; ++k) {
         long long di;
         int side;
-        if (dest(I, gi, gj, k, di, side)) {
+        if (dest<real, EDGE>(I, gi, gj, k, di, side)) {
             const int cd = c + cy(k) * PX + cx(k);
             B[(kF + k) * P + di] = fs[k];
             B[(kG + k) * P + di] = gs[k];
             const real hold = S.h[k][cd];
             B[(kH + k) * P + di] = hold + (hs[k] - hold) * S.irc[cd];
-        } else {
+        } else if (EDGE) {
             const int kb = opp(k);
             const int bc = I.bc[side];
             const real w = wgt<real>(k);
@@ -438,7 +470,8 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
     my_tiles(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
         const Tile tl = tiles[t];
-        tile_step<real, TX, TY>(insts[tl.inst], tl.x0, tl.y0, src, S);
+        if (tl.flags & kTileInterior) tile_step<real, TX, TY, false>(insts[tl.inst], tl.x0, tl.y0, src, S);
+        else tile_step<real, TX, TY, true>(insts[tl.inst], tl.x0, tl.y0, src, S);
         if (t + 1 < t1) __syncthreads();
     }
 }
@@ -461,7 +494,9 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         const Tile tl = tiles[t];
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
-        const bool inside = load_patch<real, TX, TY>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+        const bool inside = (tl.flags & kTileInterior)
+                                ? load_patch<real, TX, TY, false>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -549,7 +584,9 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         const Tile tl = tiles[t];
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
-        const bool inside = load_patch<real, TX, TY>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+        const bool inside = (tl.flags & kTileInterior)
+                                ? load_patch<real, TX, TY, false>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -632,6 +669,25 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
         for (int w = 1; w < 4; ++w) v = q == D_MAXU ? fmax(v, red[w][q]) : v + red[w][q];
         result[q] = v;
     }
+}
+
+// ---- plain copy (bandwidth and counter calibration) ----
+
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    const long long n = (long long)(bytes / sizeof(float4));
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float4*>(src),
+                       static_cast<float4*>(dst), n);
+    return hipGetLastError();
 }
 
 // ---- launchers ----

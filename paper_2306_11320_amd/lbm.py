@@ -26,7 +26,7 @@ EXPORTED = [
     "lbm_last_error", "lbm_get_state", "lbm_set_state", "lbm_checkpoint_bytes", "lbm_checkpoint_save",
     "lbm_checkpoint_load", "lbm_workspace_bytes_batch", "lbm_init_batch", "lbm_instances",
     "lbm_fields_instance", "lbm_diagnostics_instance", "lbm_tile_count", "lbm_tile_shape", "lbm_set_tile",
-    "lbm_get_tile", "lbm_set_graph_steps", "lbm_set_grid", "lbm_bytes_per_update",
+    "lbm_get_tile", "lbm_set_graph_steps", "lbm_set_grid", "lbm_bytes_per_update", "lbm_copy_probe",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
             L.lbm_get_tile.argtypes = [vp]
             L.lbm_set_graph_steps.argtypes = [vp, ip]
             L.lbm_set_grid.argtypes = [vp, ip]
+            L.lbm_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
             L.lbm_bytes_per_update.restype = C.c_size_t
             L.lbm_bytes_per_update.argtypes = [ip]
             _lib = L
@@ -304,6 +305,14 @@ def tile_shapes() -> list[tuple[int, int]]:
         _check(L.lbm_tile_shape(t, C.byref(tx), C.byref(ty)))
         out.append((tx.value, ty.value))
     return out
+
+
+def copy_probe(src, dst, stream) -> None:
+    """Plain device copy of torch tensor src into dst (same byte size) on `stream`."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n
+    _check(lib().lbm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), C.c_size_t(n),
+                                C.c_void_p(stream.cuda_stream)))
 
 
 def bytes_per_update(precision: int) -> int:

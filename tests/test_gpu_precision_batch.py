@@ -1,0 +1,146 @@
+"""FP32 deviation storage and batched lattices against the FP64 oracle.
+
+FP32 tolerances (relative L2 over the lattice, after the stated window):
+phi and T - T0 <= 1e-4, u normalised by max |u| <= 1e-3 -- single-precision
+rounding of O(1e-7) per step accumulating over ~1e3 steps with diffusive
+damping; FP64 reductions of FP32 fields within 1e-6 relative.  Storage shifted
+by (phi0, T0) in FP64 must equal the unshifted run to 1e-13 (the shift is
+exact algebra; only rounding differs).  Batched lattices must equal the same
+lattices run alone, bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_11320_amd import workloads as wl
+from tests.conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_2306_11320_amd.lbm")
+
+
+def rel_l2(a, b, scale=None):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sqrt(np.sum(b * b)) if scale is None else scale * np.sqrt(b.size)
+    return float(np.sqrt(np.sum((a - b) ** 2)) / den)
+
+
+def check_fp32(got, ref, T0, tol_phi=1e-4, tol_T=1e-4, tol_u=1e-3):
+    assert rel_l2(got["phi"], ref["phi"]) <= tol_phi, rel_l2(got["phi"], ref["phi"])
+    assert rel_l2(got["T"] - T0, ref["T"] - T0) <= tol_T, rel_l2(got["T"] - T0, ref["T"] - T0)
+    umax = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max())
+    for k in ("ux", "uy"):
+        e = rel_l2(got[k], ref[k], scale=umax)
+        assert e <= tol_u, (k, e)
+
+
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[1], wl.ALL_BCS[4], wl.ALL_BCS[0]], ids=["channel", "inlet", "periodic"])
+def test_fp32_dev_vs_oracle(bcs):
+    cfg, f0 = wl.tiny(96, 72, bc=bcs, seed=3)
+    announce("fp32_dev_vs_oracle", bcs)
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    for _ in range(2):
+        o.step(500)
+        lat.step(500)
+        check_fp32(lat.fields(), o.fields(), cfg["T_ref"])
+
+
+def test_fp32_dev_full_droplet():
+    """The benchmark workload (256 x 1024 droplet, Ma = 1, ratio 0.5), 600 steps."""
+    cfg, f0 = wl.droplet(Ma=1.0, ratio=0.5)
+    announce("fp32_dev_full_droplet")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    o.step(600)
+    lat.step(600)
+    ref, got = o.fields(), lat.fields()
+    check_fp32(got, ref, cfg["T_ref"])
+    a, b = lat.diagnostics(), o.diagnostics()
+    # FP64 reductions of FP32 fields: the light-phase volume follows the FP32
+    # populations, whose stored update is mass-neutral up to one rounding per
+    # rest population and step (|f_0| < 1, so < 6e-8 each): over 600 steps and
+    # the ~4e3 drop nodes, a random walk of that size stays far below 1e-5.
+    for k in ("mass_phi", "vol_light", "heat"):
+        assert abs(a[k] - b[k]) <= 1e-5 * abs(b[k]), (k, a[k], b[k])
+    assert abs(a["u_r"] - b["u_r"]) <= 1e-3 * abs(b["u_r"]) + 1e-12
+    assert abs(a["yc"] - b["yc"]) <= 1e-4
+
+
+def test_fp32_dev_heated_channel():
+    """20000 FP32 steps of the heated channel (errors settle: the flow is steady)."""
+    cfg, f0 = wl.heated_channel(2.0)
+    announce("fp32_dev_heated_channel")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    o.step(20000)
+    lat.step(20000)
+    check_fp32(lat.fields(), o.fields(), cfg["T_ref"])
+
+
+def test_fp64_shift_invariance():
+    cfg, f0 = wl.tiny(80, 50, bc=wl.ALL_BCS[4], seed=8)
+    announce("fp64_shift_invariance")
+    a = lbm.Lattice(cfg, f0, lbm.FP64)
+    c2 = dict(cfg, phi0_dev=1.0, T0_dev=cfg["T_ref"])
+    b = lbm.Lattice(c2, f0, lbm.FP64)
+    a.step(200)
+    b.step(200)
+    fa, fb = a.fields(), b.fields()
+    for k in ("phi", "ux", "uy", "T", "p"):
+        scale = max(np.abs(fa[k]).max(), 1e-30)
+        assert np.abs(fa[k] - fb[k]).max() <= 1e-11 * scale, k
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("f", "g", "h"):
+        assert np.abs(sa[k] - sb[k]).max() <= 1e-11 * max(1.0, np.abs(sa[k]).max()), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_equals_single_bitwise(prec):
+    P = lbm.FP64 if prec == "fp64" else lbm.FP32_DEV
+    items = [wl.tiny(70, 33, bc=wl.ALL_BCS[1], seed=1), wl.tiny(131, 64, bc=wl.ALL_BCS[4], seed=2),
+             wl.sweep_instance(128, 200, 16.0, 3.0, 1.5), wl.tiny(9, 5, bc=wl.ALL_BCS[5], seed=4)]
+    announce("batch_bitwise", prec, [(c["nx"], c["ny"]) for c, _ in items])
+    batch = lbm.Lattice.batch(items, P)
+    batch.step(37)
+    for k, (cfg, f0) in enumerate(items):
+        single = lbm.Lattice(cfg, f0, P)
+        single.step(37)
+        sa, sb = batch.get_state(k), single.get_state()
+        for fam in ("f", "g", "h", "jprev"):
+            assert np.array_equal(sa[fam], sb[fam]), (k, fam)
+        fa, fb = batch.fields(k), single.fields()
+        assert np.array_equal(fa["p"], fb["p"])
+
+
+def test_batch_persistent_grid_sizes():
+    """The persistent grid may be any size: results do not depend on it."""
+    items = [wl.tiny(100, 40, seed=1), wl.tiny(64, 90, bc=wl.ALL_BCS[4], seed=2)]
+    announce("batch_grid_sizes")
+    ref = None
+    for g in (1, 3, 7, 64, 0):
+        b = lbm.Lattice.batch(items, lbm.FP32_DEV)
+        b.set_grid(g)
+        b.step(12)
+        st = [b.get_state(k)["f"] for k in range(2)]
+        if ref is None:
+            ref = st
+        else:
+            for x, y in zip(st, ref):
+                assert np.array_equal(x, y), g
+
+
+def test_unstable_flag():
+    """A non-finite population is reported by the FP64 diagnostics."""
+    cfg, f0 = wl.tiny(40, 30, seed=1)
+    announce("unstable_flag")
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    st = lat.get_state()
+    st["g"][1, 10, 10] = np.nan
+    lat.set_state(0, g=st["g"], step=st["step"])
+    d = lat.diagnostics()
+    assert d["unstable"] and d["n_nonfinite"] >= 1
+    with pytest.raises(lbm.LbmError):
+        lat.diagnostics(raise_unstable=True)
