@@ -77,15 +77,18 @@ def prewarm(seconds: float = 0.3):
         torch.cuda.synchronize()
 
 
-def time_gpu(items, prec, steps, warmup, tile=None):
+def time_gpu(items, prec, steps, warmup, tile=None, autotune=False):
     import torch
     from paper_2306_11320_amd import lbm
     if len(items) == 1:
         lat = lbm.Lattice(items[0][0], items[0][1], prec)
     else:
         lat = lbm.Lattice.batch(items, prec)
+    tuned = None
     if tile is not None:
         lat.set_tile(tile)
+    elif autotune:
+        tuned = lat.autotune(steps_per_trial=max(2, min(50, warmup // 20 or 2)))
     lat.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -100,8 +103,28 @@ def time_gpu(items, prec, steps, warmup, tile=None):
     d = lat.diagnostics()
     nodes = sum(c["nx"] * c["ny"] for c, _ in items)
     lat.close()
-    return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes,
+    return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes, tuned=tuned,
                 mlups=nodes * steps / (ms * 1e-3) / 1e6, finite=d["n_nonfinite"] == 0, max_u=d["max_u"])
+
+
+def time_sequential(items, prec, steps, warmup):
+    """The lattices of a batch advanced one after another, each by the
+    single-lattice kernel (one launch per step): the baseline of batching."""
+    import torch
+    from paper_2306_11320_amd import lbm
+    total_ms = 0.0
+    for cfg, f0 in items:
+        lat = lbm.Lattice(cfg, f0, prec)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        lat.close()
+    return total_ms / steps
 
 
 def cpu_baseline(items, budget_s: float = 15.0):
@@ -167,7 +190,7 @@ def main():
     prewarm()
     print(f"[bench] workload {cfgdesc['workload']}: FP32 deviation storage, {args.steps} steps", file=sys.stderr,
           flush=True)
-    r32 = time_gpu(items, lbm.FP32_DEV, args.steps, args.warmup, args.tile)
+    r32 = time_gpu(items, lbm.FP32_DEV, args.steps, args.warmup, args.tile, autotune=len(items) > 1)
     bpl = lbm.bytes_per_update(lbm.FP32_DEV) * r32["nodes"]
     achieved = bpl / (r32["ms_per_step"] * 1e-3) / 1e9
     traffic = stored_traffic(args.workload, "fp32")
@@ -183,6 +206,13 @@ def main():
     ws = (2 * 27 + 2) * 4 * r32["nodes"]
     out["config"]["working_set_bytes"] = ws
     out["config"]["algorithmic_bytes_per_launch"] = bpl
+    if len(items) > 1:
+        print("[bench] sequential single-lattice baseline", file=sys.stderr, flush=True)
+        seq_ms = time_sequential(items, lbm.FP32_DEV, max(16, args.steps // 8), max(4, args.warmup // 8))
+        out["batched"] = {"tuned": r32["tuned"], "sequential_ms_per_step": round(seq_ms, 5),
+                          "batched_ms_per_step": round(r32["ms_per_step"], 5),
+                          "speedup_over_sequential": round(seq_ms / r32["ms_per_step"], 3)}
+        args.fp32_only = True
     if not args.fp32_only:
         print("[bench] FP64", file=sys.stderr, flush=True)
         r64 = time_gpu(items, lbm.FP64, args.steps, args.warmup, args.tile)

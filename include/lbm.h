@@ -174,6 +174,27 @@ int lbm_fields(lbm_ctx* c, void* d_phi, void* d_ux, void* d_uy, void* d_T, void*
  */
 int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
 
+/* Modes of lbm_reinit_fields. */
+enum { LBM_REINIT_EQUILIBRIUM = 0, LBM_REINIT_SHIFT = 1 };
+
+/*
+ * Re-initialises lattice `instance` from caller-owned device fields (nx*ny
+ * elements each, x fastest, FP64 if in_dtype is LBM_OUT_F64, FP32 if
+ * LBM_OUT_F32) of phi, u, T and the pressure p (d_p may be NULL).
+ *   LBM_REINIT_EQUILIBRIUM: populations := the equilibria of Eqs. (9), (17)
+ *     and (33) at the given fields (p = 0 if d_p is NULL);
+ *   LBM_REINIT_SHIFT: populations += eq(given fields) - eq(current fields of
+ *     the lattice), so their non-equilibrium part is kept (the current p is
+ *     kept if d_p is NULL).
+ * In both modes (phi u) of the previous level is set to the current one, so
+ * the first time derivative of (phi u) after the restart is zero.  The step
+ * counter is kept.  Asynchronous on the lattice's stream; the fields must stay
+ * valid until it has run.  Errors: LBM_EINVAL (NULL field, unknown dtype or
+ * mode, bad instance), LBM_EHIP.
+ */
+int lbm_reinit_fields(lbm_ctx* c, int instance, const void* d_phi, const void* d_ux, const void* d_uy,
+                      const void* d_T, const void* d_p, int in_dtype, int mode);
+
 /* Destroys the context (synchronizes its stream first).  NULL is accepted. */
 int lbm_destroy(lbm_ctx* c);
 
@@ -243,6 +264,21 @@ int lbm_set_graph_steps(lbm_ctx* c, int steps);
 /* Sets the number of workgroups of the persistent grid (0 = one workgroup per
  * tile, the default for a single lattice). */
 int lbm_set_grid(lbm_ctx* c, int workgroups);
+
+/* Workgroups of the persistent grid in use (0: one per tile; -1: sized at the
+ * next step). */
+int lbm_get_grid(const lbm_ctx* c);
+
+/*
+ * Tile autotuner: times `steps_per_trial` steps with every compiled tile shape
+ * (and, for a batched context, a persistent grid of one and two resident waves
+ * of workgroups and one workgroup per tile) with HIP events on the context's
+ * stream, then keeps the fastest.  Tile shape and grid change only the launch,
+ * never the per-node arithmetic, so the trial steps are ordinary steps: the
+ * lattices advance by (trials x (steps_per_trial + 1)) steps.  Synchronizes.
+ * Outputs may be NULL.  Errors: LBM_EINVAL, LBM_EHIP.
+ */
+int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid, float* best_ms_per_step);
 
 /* Algorithmic HBM traffic of one lattice update: 27 populations read and
  * written plus (phi u) of the previous level read and written. */

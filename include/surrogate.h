@@ -1,0 +1,102 @@
+/*
+ * surrogate.h -- C ABI of the gfx950 kernels of the learned surrogate that
+ * advances lattice states of the thermocapillary lattice Boltzmann scheme
+ * (arXiv:2306.11320) by a fixed number of time steps.  Not part of the paper's
+ * method: the lattice update of lbm.h remains the reference and the fallback.
+ *
+ * Network: 3x3 convolutions over frames periodic in x and zero-padded in y;
+ * BF16 activations and weights, FP32 accumulation on the matrix cores
+ * (v_mfma_f32_32x32x16_bf16), FP32 bias, weight gradients, master weights and
+ * Adam state.
+ *
+ * Layouts (all device memory owned by the caller; every call is asynchronous
+ * on `stream` and returns 0 or a negative error code, see sur_last_error):
+ *   activations  NHWC, element (n, y, x, c) at ((n*H + y)*W + x)*C + c, with
+ *                C = 32 (network input: C = 8), BF16;
+ *   weights      [co = 32][tap = 9][ci], tap = 3*(dy+1) + (dx+1), BF16;
+ *   W            a multiple of 32; pointers 16-byte aligned.
+ */
+#ifndef SURROGATE_H
+#define SURROGATE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out = [mask > 0] * (conv(A, w) + bias) + res, A = max(in, 0) if relu_in else
+ * in; in has cin in {8, 32} channels; out has 32 channels, FP32 if out_f32
+ * else BF16.  bias, res and mask may be NULL (res has out's type; mask is BF16
+ * with 32 channels). */
+int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias, const void* d_res,
+                const void* d_mask, void* d_out, int out_f32, int relu_in, int n, int h, int w, void* stream);
+
+/* Weights of the adjoint (input-gradient) convolution of a layer with cin
+ * input channels: wt[ci][8 - tap][co] = w[co][tap][ci], 32 x 9 x 32 BF16.
+ * sur_conv3x3(dy, 32, wt, ...) then computes the gradient with respect to the
+ * layer's input (periodic x, zero-padded y: the exact adjoint). */
+int sur_adjoint_weights(const void* d_w, int cin, void* d_wt, void* stream);
+
+/* Weight gradient dW[co][tap][ci] = sum_p dy[p][co] A[p + offset(tap)][ci]
+ * (A = max(in, 0) if relu_in) into d_out (32*9*cin FP32), through `groups`
+ * per-workgroup partial sums in d_part (sur_wgrad_scratch_floats floats),
+ * summed in a fixed order. */
+int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, int n, int h, int w, float* d_part,
+                    int groups, float* d_out, void* stream);
+size_t sur_wgrad_scratch_floats(int cin, int groups);
+
+/* Bias gradient db[co] = sum_p dy[p][co] (32 FP32), through 32*groups partials. */
+int sur_bias_grad(const void* d_dy, int64_t npix, float* d_part, int groups, float* d_out, void* stream);
+
+/* One Adam step (bias-corrected, step t >= 1) on n FP32 master values; writes
+ * the BF16 copy d_pb. */
+int sur_adam(float* d_p, const float* d_g, float* d_m1, float* d_m2, void* d_pb, int64_t n, float lr, float beta1,
+             float beta2, float eps, int t, void* stream);
+
+/* Squared error of the predicted increment delta[:, 0:nout] (FP32, 32
+ * channels) against the target increment (nout FP32 channels, 1 <= nout <= 32):
+ * per-workgroup partial sums into d_part[groups]; gradient
+ * 2 (delta - target) * scale into d_grad (BF16, 32 channels, zero beyond nout). */
+int sur_mse(const float* d_delta, const float* d_target, int64_t npix, int nout, float scale, void* d_grad,
+            float* d_part, int groups, void* stream);
+
+/* Scalings of one lattice's state.  The state is five FP32 fields of h x w
+ * values (x fastest): phi, ux, uy, T and the pressure p, passed as a host
+ * array of 5 device pointers in that order. */
+typedef struct {
+    float u;          /* velocity scale U (> 0) */
+    float dT;         /* temperature scale (> 0) */
+    float t_a, t_b;   /* rest temperature profile T_rest(y) = t_a + t_b y, y = row index */
+    float P;          /* pressure scale (> 0) */
+    float c4, c5;     /* constant conditioning inputs (channels 4 and 5) */
+    float inc[5];     /* unit of the learned increment of phi, ux, uy, T, p (> 0) */
+} sur_scales;
+
+/* Network input of one frame: 8 BF16 channels (phi, ux/u, uy/u,
+ * (T - T_rest(y))/dT, c4, c5, p/P, 0) into d_x (h*w*8 values). */
+int sur_pack(const float* const* d_f, int h, int w, const sur_scales* scales, void* d_x, void* stream);
+/* Target increment between states f0 and f1: (f1_c - f0_c) / inc[c] for the
+ * five fields, 5 FP32 channels per pixel into d_t. */
+int sur_pack_target(const float* const* d_f0, const float* const* d_f1, int64_t npix, const sur_scales* scales,
+                    float* d_t, void* stream);
+/* Advances the five fields in place by a predicted increment:
+ * f_c += delta[:, c] inc[c], c = 0..4 (delta: FP32, 32 channels). */
+int sur_advance(const float* d_delta, int64_t npix, const sur_scales* scales, float* const* d_f, void* stream);
+/* Light-phase volume sum (1 - phi)/2 of a frame, in FP64, into *d_out (device),
+ * through `groups` partials in d_part (8*groups doubles), summed in a fixed order. */
+int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int groups, double* d_out, void* stream);
+/* Judge of a predicted frame a against a lattice frame b (first four fields):
+ * d_out[2c] = sum (a_c - b_c)^2 and d_out[2c+1] = sum (b_c - rest_c)^2 for
+ * c = phi, ux, uy, T with rest = (1, 0, 0, T_rest(y)), FP64, through `groups`
+ * partials in d_part (8*groups doubles), summed in a fixed order. */
+int sur_judge(const float* const* d_a, const float* const* d_b, int h, int w, const sur_scales* scales,
+              double* d_part, int groups, double* d_out, void* stream);
+
+const char* sur_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURROGATE_H */

@@ -345,7 +345,7 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
             if (e != hipSuccess) return bail(fail(LBM_EHIP, "copy of initial fields: %s", hipGetErrorString(e)));
         }
         lbm::InitArgs ia{ps[k].phi0_dev, ps[k].T0_dev, 0.5 * (ps[k].rho_l + ps[k].rho_h),
-                         0.5 * (ps[k].rho_h - ps[k].rho_l)};
+                         0.5 * (ps[k].rho_h - ps[k].rho_l), 0, 0};
         e = lbm::launch_init((int)c->prec, static_cast<char*>(c->d_insts) + k * isz, (long long)nn, staged, ia, 0,
                              c->stream);
         if (e != hipSuccess) return bail(fail(LBM_EHIP, "init kernel: %s", hipGetErrorString(e)));
@@ -439,6 +439,36 @@ int lbm_fields_instance(lbm_ctx* c, int instance, void* d_phi, void* d_ux, void*
     HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile] + L.tile_off[c->tile],
                                L.tile_cnt[c->tile], (int)(c->step & 1), d_phi, d_ux, d_uy, d_T, d_p,
                                out_dtype == LBM_OUT_F32, 0, c->stream));
+    return LBM_OK;
+}
+
+int lbm_reinit_fields(lbm_ctx* c, int instance, const void* d_phi, const void* d_ux, const void* d_uy,
+                      const void* d_T, const void* d_p, int in_dtype, int mode)
+{
+    int rc = check_instance(c, instance);
+    if (rc) return rc;
+    if (!d_phi || !d_ux || !d_uy || !d_T) return fail(LBM_EINVAL, "NULL field");
+    if (in_dtype != LBM_OUT_F64 && in_dtype != LBM_OUT_F32) return fail(LBM_EINVAL, "unknown input dtype");
+    if (mode != LBM_REINIT_EQUILIBRIUM && mode != LBM_REINIT_SHIFT) return fail(LBM_EINVAL, "unknown reinit mode");
+    const Layout& L = c->lay[instance];
+    const lbm_params& p = c->params[instance];
+    const long long n = (long long)L.nx * L.ny;
+    const int lvl = (int)(c->step & 1);
+    const size_t isz = inst_size(c->prec);
+    const void* inst = static_cast<char*>(c->d_insts) + instance * isz;
+    const lbm::Tile* tiles = c->d_tiles[c->tile] + L.tile_off[c->tile];
+    // the other time level is free until the next step: it holds the staged
+    // new fields (planes 0..4) and, when shifting, the current ones (5..9)
+    double* staged = reinterpret_cast<double*>(c->ws + L.pop_off[lvl ^ 1]);
+    HIP_TRY(lbm::launch_stage(d_phi, d_ux, d_uy, d_T, d_p, in_dtype == LBM_OUT_F32, n, staged, c->stream));
+    if (mode == LBM_REINIT_SHIFT)
+        HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, tiles, L.tile_cnt[c->tile], lvl, staged + 5 * n,
+                                   staged + 6 * n, staged + 7 * n, staged + 8 * n, staged + 9 * n, 0, 0, c->stream));
+    lbm::InitArgs ia{p.phi0_dev, p.T0_dev, 0.5 * (p.rho_l + p.rho_h), 0.5 * (p.rho_h - p.rho_l), d_p != nullptr,
+                     mode == LBM_REINIT_SHIFT};
+    HIP_TRY(lbm::launch_init((int)c->prec, inst, n, staged, ia, lvl, c->stream));
+    HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, tiles, L.tile_cnt[c->tile], lvl, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, 0, 1, c->stream));
     return LBM_OK;
 }
 
@@ -746,6 +776,72 @@ int lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* hip_strea
     HIP_TRY(lbm::launch_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(hip_stream)));
     return LBM_OK;
 }
+
+int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid, float* best_ms)
+{
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int saved_graph = c->graph_steps;
+    drop_graph(c);
+    c->graph_steps = 0;  // plain launches: every trial sees the same launch path
+    float best = 1e30f;
+    int bt = c->tile, bg = c->grid;
+    int rc = LBM_OK;
+    for (int t = 0; t < lbm::kTileCount && rc == LBM_OK; ++t) {
+        int grids[3] = {0, 0, 0}, ng = 1;
+        if (c->n > 1) {
+            int per_cu = 1;
+            if (lbm::step_occupancy((int)c->prec, t, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+            const int resident = per_cu * (cus > 0 ? cus : 256);
+            grids[0] = resident < c->ntiles[t] ? resident : c->ntiles[t];
+            grids[1] = 2 * resident < c->ntiles[t] ? 2 * resident : c->ntiles[t];
+            grids[2] = c->ntiles[t];
+            ng = 3;
+        }
+        for (int q = 0; q < ng && rc == LBM_OK; ++q) {
+            c->tile = t;
+            c->grid = grids[q];
+            // one untimed step in this configuration, then the timed trial
+            rc = lbm_step(c, 1);
+            if (rc) break;
+            hipError_t e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) rc = lbm_step(c, steps_per_trial);
+            if (rc) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(LBM_EHIP, "autotune timing: %s", hipGetErrorString(e));
+                break;
+            }
+            ms /= (float)steps_per_trial;
+            if (ms < best) {
+                best = ms;
+                bt = t;
+                bg = grids[q];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tile = bt;
+    c->grid = bg;
+    c->graph_steps = saved_graph;
+    if (rc) return rc;
+    if (best_tile) *best_tile = bt;
+    if (best_grid) *best_grid = bg;
+    if (best_ms) *best_ms = best;
+    return LBM_OK;
+}
+
+int lbm_get_grid(const lbm_ctx* c) { return c ? c->grid : -1; }
 
 size_t lbm_bytes_per_update(int precision)
 {

@@ -56,6 +56,8 @@ struct DiagArgs {
 
 struct InitArgs {
     double phi0, T0, rho_a, rho_b;
+    int has_p;  // staged pressure plane present (else p = 0, or the current p when shifting)
+    int shift;  // add eq(new) - eq(current fields in staged planes 5..9) instead of replacing
 };
 
 // Compiled tile shapes (TX x TY nodes, one work-item per node).
@@ -76,10 +78,17 @@ hipError_t launch_fields(int prec, int tile, const void* insts, const Tile* tile
 // T (n_nodes each, x fastest, contiguous) into time level `src`.
 hipError_t launch_init(int prec, const void* inst_dev, long long n_nodes, const double* staged, const InitArgs& a,
                        int src, hipStream_t s);
+// Device fields (FP32 if in_f32, else FP64) into the FP64 staging layout of launch_init.
+hipError_t launch_stage(const void* phi, const void* ux, const void* uy, const void* T, const void* p, int in_f32,
+                        long long n,
+                        double* staged, hipStream_t s);
 // Per-workgroup FP64 partial sums (D_COUNT each) then a deterministic final sum
 // into `result` (D_COUNT doubles).
 hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src,
                        const DiagArgs& a, double* partials, double* result, hipStream_t s);
+
+// Resident workgroups of the step kernel per compute unit.
+hipError_t step_occupancy(int prec, int tile, int* blocks_per_cu);
 
 // Plain 16-byte-vector copy of `bytes` (a multiple of 16).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

@@ -533,7 +533,7 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
 // g_i = rho s_i(u), h_i = w_i T, stored as deviations.  Computed in FP64.
 template <typename real>
 __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __restrict__ staged, double phi0,
-                       double T0, double rho_a, double rho_b, int src)
+                       double T0, double rho_a, double rho_b, int has_p, int shift, int src)
 {
     const Inst<real>& I = insts[0];
     const long long n = (long long)I.nx * I.ny;
@@ -541,18 +541,73 @@ __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __res
     if (x >= n) return;
     const int i = (int)(x % I.nx), j = (int)(x / I.nx);
     const double phi = staged[x], ux = staged[n + x], uy = staged[2 * n + x], T = staged[3 * n + x];
-    const double rho = rho_a + rho_b * phi;
-    const double uu = ux * ux + uy * uy;
     real* __restrict__ A = I.pop[src];
     const long long P = I.plane, idx = (long long)j * I.pitch + i;
+    if (!shift) {
+        const double p = has_p ? staged[4 * n + x] : 0.0;
+        const double rho = rho_a + rho_b * phi;
+        const double uu = ux * ux + uy * uy;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double w = wgt<double>(k);
+            const double cu = cx(k) * ux + cy(k) * uy;
+            A[(kF + k) * P + idx] = (real)(w * ((phi - phi0) + 3.0 * phi * cu));
+            A[(kG + k) * P + idx] =
+                (real)(3.0 * p * (w - (k == 0 ? 1.0 : 0.0)) + rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+            A[(kH + k) * P + idx] = (real)(w * (T - T0));
+        }
+        return;
+    }
+    // shift: add eq(new) - eq(current) to the populations, keeping their
+    // non-equilibrium part; the current fields sit in staged planes 5..9
+    const double phc = staged[5 * n + x], uxc = staged[6 * n + x], uyc = staged[7 * n + x];
+    const double Tc = staged[8 * n + x], pc = staged[9 * n + x];
+    const double p = has_p ? staged[4 * n + x] : pc;
+    const double rho = rho_a + rho_b * phi, rhoc = rho_a + rho_b * phc;
+    const double uu = ux * ux + uy * uy, uuc = uxc * uxc + uyc * uyc;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const double w = wgt<double>(k);
-        const double cu = cx(k) * ux + cy(k) * uy;
-        A[(kF + k) * P + idx] = (real)(w * ((phi - phi0) + 3.0 * phi * cu));
-        A[(kG + k) * P + idx] = (real)(rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        A[(kH + k) * P + idx] = (real)(w * (T - T0));
+        const double cu = cx(k) * ux + cy(k) * uy, cuc = cx(k) * uxc + cy(k) * uyc;
+        const double df = w * ((phi - phc) + 3.0 * (phi * cu - phc * cuc));
+        const double dg = 3.0 * (p - pc) * (w - (k == 0 ? 1.0 : 0.0)) +
+                          w * (rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - rhoc * (3.0 * cuc + 4.5 * cuc * cuc - 1.5 * uuc));
+        const double dh = w * (T - Tc);
+        A[(kF + k) * P + idx] = (real)((double)A[(kF + k) * P + idx] + df);
+        A[(kG + k) * P + idx] = (real)((double)A[(kG + k) * P + idx] + dg);
+        A[(kH + k) * P + idx] = (real)((double)A[(kH + k) * P + idx] + dh);
     }
+}
+
+// Gathers device fields (FP32 or FP64, x fastest) into the FP64 staging layout
+// k_init reads: [phi | ux | uy | T | p], n values each (p only if given).
+template <typename in_t>
+__global__ void k_stage(const in_t* __restrict__ phi, const in_t* __restrict__ ux, const in_t* __restrict__ uy,
+                        const in_t* __restrict__ T, const in_t* __restrict__ p, long long n,
+                        double* __restrict__ staged)
+{
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    staged[x] = (double)phi[x];
+    staged[n + x] = (double)ux[x];
+    staged[2 * n + x] = (double)uy[x];
+    staged[3 * n + x] = (double)T[x];
+    if (p) staged[4 * n + x] = (double)p[x];
+}
+
+hipError_t launch_stage(const void* phi, const void* ux, const void* uy, const void* T, const void* p, int in_f32,
+                        long long n, double* staged, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (in_f32)
+        hipLaunchKernelGGL(k_stage<float>, grid, dim3(256), 0, s, static_cast<const float*>(phi),
+                           static_cast<const float*>(ux), static_cast<const float*>(uy),
+                           static_cast<const float*>(T), static_cast<const float*>(p), n, staged);
+    else
+        hipLaunchKernelGGL(k_stage<double>, grid, dim3(256), 0, s, static_cast<const double*>(phi),
+                           static_cast<const double*>(ux), static_cast<const double*>(uy),
+                           static_cast<const double*>(T), static_cast<const double*>(p), n, staged);
+    return hipGetLastError();
 }
 
 // ---- FP64 diagnostics ----
@@ -745,6 +800,22 @@ hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles,
 #undef STEP32
 }
 
+template <typename real, int TX, int TY>
+static hipError_t occ_t(int* blocks)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY>, TX * TY, 0);
+}
+
+hipError_t step_occupancy(int prec, int tile, int* blocks_per_cu)
+{
+#define O64(a, b) occ_t<double, a, b>(blocks_per_cu)
+#define O32(a, b) occ_t<float, a, b>(blocks_per_cu)
+    if (prec == 0) { LBM_TILE_SWITCH(tile, O64) }
+    LBM_TILE_SWITCH(tile, O32)
+#undef O64
+#undef O32
+}
+
 hipError_t launch_fields(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int src, void* phi,
                          void* ux, void* uy, void* T, void* p, int out_f32, int jprev_out, hipStream_t s)
 {
@@ -762,10 +833,10 @@ hipError_t launch_init(int prec, const void* inst_dev, long long n_nodes, const 
     const dim3 grid((unsigned)((n_nodes + 255) / 256));
     if (prec == 0)
         hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, s, static_cast<const Inst<double>*>(inst_dev), staged,
-                           a.phi0, a.T0, a.rho_a, a.rho_b, src);
+                           a.phi0, a.T0, a.rho_a, a.rho_b, a.has_p, a.shift, src);
     else
         hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, s, static_cast<const Inst<float>*>(inst_dev), staged,
-                           a.phi0, a.T0, a.rho_a, a.rho_b, src);
+                           a.phi0, a.T0, a.rho_a, a.rho_b, a.has_p, a.shift, src);
     return hipGetLastError();
 }
 

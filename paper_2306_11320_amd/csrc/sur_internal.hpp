@@ -1,0 +1,38 @@
+// Internal declarations of the surrogate kernels (sur_kernels.hip) used by the
+// C ABI in sur_api.hip.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sur {
+
+typedef __bf16 bf16;
+
+hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const void* res, const bf16* mask,
+                void* out, int out_f32, int relu_in, int N, int H, int W, hipStream_t s);
+hipError_t adjoint_weights(const bf16* w, int cin, bf16* wt, hipStream_t s);
+hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int N, int H, int W, float* part, int groups,
+                 float* out, hipStream_t s);
+hipError_t bgrad(const bf16* dy, long long npix, float* part, int groups, float* out, hipStream_t s);
+hipError_t adam(float* p, const float* g, float* m1, float* m2, bf16* pb, long long n, float lr, float b1, float b2,
+                float eps, int t, hipStream_t s);
+// The five FP32 state fields of a frame: phi, ux, uy, T, p.
+struct State5 {
+    const float* v[5];
+};
+// Scalings of a frame (mirrors sur_scales of the C ABI).
+struct Scales {
+    float u, dT, t_a, t_b, P, c4, c5;
+    float inc[5];
+};
+
+hipError_t mse(const float* delta, const float* target, long long npix, int nout, float scale, bf16* grad,
+               float* part, int groups, hipStream_t s);
+hipError_t pack(const State5& f, long long npix, int w, const Scales& sc, bf16* x, hipStream_t s);
+hipError_t pack_target(const State5& f0, const State5& f1, long long npix, const Scales& sc, float* t, hipStream_t s);
+hipError_t advance(const float* delta, long long npix, const Scales& sc, const State5& f, hipStream_t s);
+hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,
+                      int groups, double* out, hipStream_t s);
+
+}  // namespace sur

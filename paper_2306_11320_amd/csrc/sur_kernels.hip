@@ -1,0 +1,418 @@
+// gfx950 kernels of the learned surrogate: a residual network of 3x3
+// convolutions over (phi, u_x, u_y, T) frames that advances the lattice state
+// by a fixed number of time steps.  Activations and weights are BF16, all
+// products accumulate in FP32 on the matrix cores (v_mfma_f32_32x32x16_bf16).
+//
+// Layouts: activations NHWC with C = 32 channels (the 4-channel network input
+// is padded to C = 8), weights [co = 32][tap = 9][ci] (rows beyond the layer's
+// real output channels are zero), taps ordered (dy, dx) = (-1..1, -1..1) with
+// tap = 3 (dy + 1) + (dx + 1).  Frames are periodic in x and zero-padded in y
+// (x is the periodic direction of the lattices the surrogate stands in for).
+//
+// Convolution as an implicit GEMM: one wave computes a 32-pixel x 32-channel
+// output block; the reduction runs over K = 9 Cin in blocks of 16, where each
+// lane's 8 consecutive K entries are 8 consecutive channels of one tap, i.e.
+// one 16-byte load from NHWC memory and one from the weights.
+// MFMA 32x32x16 operand layout (checked on the device): lane l holds
+// A[l % 32][8 (l / 32) + j] and B[8 (l / 32) + j][l % 32], j = 0..7; the
+// accumulator element i of lane l is C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+#include "sur_internal.hpp"
+
+namespace sur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline bf16x8 load8(const bf16* p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+__device__ inline bf16x8 relu8(bf16x8 v)
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (float)v[j] > 0.f ? v[j] : (__bf16)0.f;
+    return v;
+}
+
+__device__ inline float to_f(bf16 v) { return (float)v; }
+
+// out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + dy, x + dx, ci) W[co][tap][ci] )
+// A = relu(in) if relu_in.  Epilogue: + bias[co]; then, if mask, zero where
+// mask <= 0; then, if res, + res.  The output is FP32 or BF16.
+__global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, int cin, const bf16* __restrict__ w,
+                                              const float* __restrict__ bias, const void* __restrict__ res,
+                                              const bf16* __restrict__ mask, void* __restrict__ out, int out_f32,
+                                              int relu_in, int N, int H, int W)
+{
+    const int lane = threadIdx.x % 64;
+    const long long seg = (long long)blockIdx.x * 4 + threadIdx.x / 64;  // 32-pixel segment
+    const int segs_per_row = W / 32;
+    if (seg >= (long long)N * H * segs_per_row) return;
+    const int x0 = (int)(seg % segs_per_row) * 32;
+    const long long ny = seg / segs_per_row;
+    const int y = (int)(ny % H), n = (int)(ny / H);
+    const int m = lane % 32, kh = lane / 32;
+    const int K = 9 * cin;
+    f32x16 acc = {};
+    for (int kb = 0; kb < K; kb += 16) {
+        const int kk = kb + 8 * kh;
+        bf16x8 a = {}, b = {};
+        if (kk < K) {
+            const int tap = kk / cin, ci = kk % cin;
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            const int yy = y + dy;
+            int xx = x0 + m + dx;
+            xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+            if (yy >= 0 && yy < H) {
+                a = load8(in + (((long long)n * H + yy) * W + xx) * cin + ci);
+                if (relu_in) a = relu8(a);
+            }
+            b = load8(w + ((long long)m * 9 + tap) * cin + ci);  // column co = lane % 32
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int co = lane % 32;
+    const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int px = x0 + 8 * (i / 4) + 4 * kh + (i % 4);
+        const long long idx = (((long long)n * H + y) * W + px) * 32 + co;
+        float v = acc[i] + bv;
+        if (mask && !(to_f(mask[idx]) > 0.f)) v = 0.f;
+        if (out_f32) {
+            if (res) v += static_cast<const float*>(res)[idx];
+            static_cast<float*>(out)[idx] = v;
+        } else {
+            if (res) v += to_f(static_cast<const bf16*>(res)[idx]);
+            static_cast<bf16*>(out)[idx] = (bf16)v;
+        }
+    }
+}
+
+// Weights of the adjoint convolution: wt[ci][8 - tap][co] = w[co][tap][ci]
+// (channels swapped, taps mirrored).  wt has cin_t = 32 input channels and
+// cout rows; rows ci >= cin of w stay zero.
+__global__ void k_adjoint_weights(const bf16* __restrict__ w, int cin, bf16* __restrict__ wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 32 x 9 x 32
+    if (i >= 32 * 9 * 32) return;
+    const int co = i % 32, tap = (i / 32) % 9, ci = i / (32 * 9);
+    wt[((long long)ci * 9 + (8 - tap)) * 32 + co] = ci < cin ? w[((long long)co * 9 + tap) * cin + ci] : (bf16)0.f;
+}
+
+// Weight gradient partials: part[g][co][kk] = sum over the workgroup's pixels of
+// dy[p][co] * A(p + off(tap))[ci], kk = tap * cin + ci, A = relu(in) if relu_in.
+// Each workgroup walks whole 32-pixel segments; LDS holds dy of the segment
+// and the three input rows it touches.
+__global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, const bf16* __restrict__ in, int cin,
+                                               int relu_in, int N, int H, int W, float* __restrict__ part,
+                                               int ntiles_n)
+{
+    __shared__ bf16 sdy[32][33];          // [pixel][co] (+1 pad)
+    __shared__ bf16 sa[3][34][33];        // [row][pixel + 1][ci] (+1 pad), cin <= 32
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int segs_per_row = W / 32;
+    const long long nseg = (long long)N * H * segs_per_row;
+    const long long s0 = (long long)blockIdx.x * nseg / gridDim.x, s1 = (long long)(blockIdx.x + 1) * nseg / gridDim.x;
+    const int K = 9 * cin;
+    f32x16 acc[3] = {};
+    for (long long seg = s0; seg < s1; ++seg) {
+        const int x0 = (int)(seg % segs_per_row) * 32;
+        const long long nyy = seg / segs_per_row;
+        const int y = (int)(nyy % H), n = (int)(nyy / H);
+        __syncthreads();
+        for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+            const int p = q / 32, c = q % 32;
+            sdy[p][c] = dy[(((long long)n * H + y) * W + x0 + p) * 32 + c];
+        }
+        for (int q = threadIdx.x; q < 3 * 34 * 32; q += 256) {
+            const int c = q % 32, p = (q / 32) % 34, r = q / (32 * 34);
+            const int yy = y + r - 1;
+            int xx = x0 + p - 1;
+            xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+            bf16 v = (bf16)0.f;
+            if (c < cin && yy >= 0 && yy < H) {
+                v = in[(((long long)n * H + yy) * W + xx) * cin + c];
+                if (relu_in && !(to_f(v) > 0.f)) v = (bf16)0.f;
+            }
+            sa[r][p][c] = v;
+        }
+        __syncthreads();
+        // GEMM: M = co (32), N = kk (tiles of 32), K = 32 pixels in two blocks of 16
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int tile = wave + 4 * t;
+            if (tile >= ntiles_n) break;
+            for (int kb = 0; kb < 32; kb += 16) {
+                bf16x8 a, b;
+                const int p0 = kb + 8 * (lane / 32);
+                const int kk = tile * 32 + lane % 32;
+                const int tap = kk / cin, ci = kk % cin;
+                const bool valid = kk < K;
+                const int dyy = valid ? tap / 3 : 0, dxx = valid ? tap % 3 : 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    a[j] = sdy[p0 + j][lane % 32];
+                    b[j] = valid ? sa[dyy][p0 + j + dxx][ci] : (bf16)0.f;
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile >= ntiles_n) break;
+        const int kk = tile * 32 + lane % 32;
+        if (kk >= K) continue;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int co = 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+            part[((long long)blockIdx.x * 32 + co) * K + kk] = acc[t][i];
+        }
+    }
+}
+
+// Bias gradient partials: part[g][co] = sum over the workgroup's pixels of dy[p][co].
+__global__ __launch_bounds__(256) void k_bgrad(const bf16* __restrict__ dy, long long npix, float* __restrict__ part)
+{
+    __shared__ float red[8][32];
+    const int co = threadIdx.x % 32, r = threadIdx.x / 32;
+    const long long p0 = (long long)blockIdx.x * npix / gridDim.x, p1 = (long long)(blockIdx.x + 1) * npix / gridDim.x;
+    float s = 0.f;
+    for (long long p = p0 + r; p < p1; p += 8) s += to_f(dy[p * 32 + co]);
+    red[r][co] = s;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.f;
+        for (int q = 0; q < 8; ++q) t += red[q][threadIdx.x];
+        part[(long long)blockIdx.x * 32 + threadIdx.x] = t;
+    }
+}
+
+// out[j] = sum_g part[g][j] in the order g = 0, 1, ... (deterministic).
+__global__ void k_reduce(const float* __restrict__ part, int ngroups, long long width, float* __restrict__ out)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= width) return;
+    float s = 0.f;
+    for (int g = 0; g < ngroups; ++g) s += part[(long long)g * width + j];
+    out[j] = s;
+}
+
+// Adam on FP32 master weights; writes the BF16 copy used by the convolutions.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m1,
+                       float* __restrict__ m2, bf16* __restrict__ pb, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float a = b1 * m1[i] + (1.f - b1) * g;
+    const float b = b2 * m2[i] + (1.f - b2) * g * g;
+    m1[i] = a;
+    m2[i] = b;
+    const float v = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    p[i] = v;
+    pb[i] = (bf16)v;
+}
+
+// Squared error of the predicted increment delta (channels 0..nout-1) against
+// the target increment (nout channels): per-workgroup partial sums, and the
+// gradient 2 (delta - target) * scale as BF16 (channels >= nout zero).
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ delta /*C=32*/,
+                                             const float* __restrict__ target /*C=nout*/, long long npix, int nout,
+                                             float scale, bf16* __restrict__ grad /*C=32*/, float* __restrict__ part)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < npix * 32;
+         q += (long long)gridDim.x * blockDim.x) {
+        const long long p = q / 32;
+        const int c = (int)(q % 32);
+        float g = 0.f;
+        if (c < nout) {
+            const float e = delta[q] - target[p * nout + c];
+            s += e * e;
+            g = 2.f * e * scale;
+        }
+        grad[q] = (bf16)g;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Network input from the five FP32 state fields of one frame (x fastest):
+// channels (phi, ux / U, uy / U, (T - T_rest(y)) / dT, c4, c5, p / P, 0), BF16.
+__global__ void k_pack(State5 f, long long npix, int w, Scales sc, bf16* __restrict__ x)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float y = (float)(p / w);
+    bf16* o = x + p * 8;
+    o[0] = (bf16)f.v[0][p];
+    o[1] = (bf16)(f.v[1][p] / sc.u);
+    o[2] = (bf16)(f.v[2][p] / sc.u);
+    o[3] = (bf16)((f.v[3][p] - (sc.t_a + sc.t_b * y)) / sc.dT);
+    o[4] = (bf16)sc.c4;
+    o[5] = (bf16)sc.c5;
+    o[6] = (bf16)(f.v[4][p] / sc.P);
+    o[7] = (bf16)0.f;
+}
+
+// Target increment between two states, channel c in units of inc[c]: FP32, C = 5.
+__global__ void k_pack_target(State5 f0, State5 f1, long long npix, Scales sc, float* __restrict__ t)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) t[p * 5 + c] = (f1.v[c][p] - f0.v[c][p]) / sc.inc[c];
+}
+
+// Advances the five FP32 state fields in place: f_c += delta_c inc[c].
+__global__ void k_advance(const float* __restrict__ delta, long long npix, Scales sc, State5 f)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        float* v = const_cast<float*>(f.v[c]);
+        v[p] = v[p] + delta[p * 32 + c] * sc.inc[c];
+    }
+}
+
+// Per-workgroup FP64 partial sums over one frame: the light-phase volume
+// sum (1 - phi) / 2 if b is null, else, for the channels phi, ux, uy, T,
+// sum (a - b)^2 and sum (b - rest)^2 with rest = (1, 0, 0, T_rest(y)).
+__global__ __launch_bounds__(256) void k_frame_sums(State5 a, State5 b, int has_b, long long npix, int w, Scales sc,
+                                                    double* __restrict__ part)
+{
+    __shared__ double red[8][256];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix;
+         p += (long long)gridDim.x * blockDim.x) {
+        if (!has_b) {
+            acc[0] += 0.5 * (1.0 - (double)a.v[0][p]);
+            continue;
+        }
+        const double rest[4] = {1.0, 0.0, 0.0, (double)sc.t_a + (double)sc.t_b * (double)(p / w)};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double bv = b.v[c][p];
+            const double d = (double)a.v[c][p] - bv, r = bv - rest[c];
+            acc[2 * c] += d * d;
+            acc[2 * c + 1] += r * r;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) part[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sums the partials of k_frame_sums over workgroups in a fixed order.
+__global__ void k_frame_final(const double* __restrict__ part, int groups, double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= 8) return;
+    double s = 0.0;
+    for (int g = 0; g < groups; ++g) s += part[g * 8 + k];
+    out[k] = s;
+}
+
+// ---- launchers ----
+
+hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const void* res, const bf16* mask,
+                void* out, int out_f32, int relu_in, int N, int H, int W, hipStream_t s)
+{
+    const long long segs = (long long)N * H * (W / 32);
+    hipLaunchKernelGGL(k_conv, dim3((unsigned)((segs + 3) / 4)), dim3(256), 0, s, in, cin, w, bias, res, mask, out,
+                       out_f32, relu_in, N, H, W);
+    return hipGetLastError();
+}
+
+hipError_t adjoint_weights(const bf16* w, int cin, bf16* wt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint_weights, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, s, w, cin, wt);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int N, int H, int W, float* part, int groups,
+                 float* out, hipStream_t s)
+{
+    const int ntiles_n = (9 * cin + 31) / 32;
+    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(256), 0, s, dy, in, cin, relu_in, N, H, W, part, ntiles_n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long width = 32LL * 9 * cin;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, s, part, groups, width, out);
+    return hipGetLastError();
+}
+
+hipError_t bgrad(const bf16* dy, long long npix, float* part, int groups, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bgrad, dim3(groups), dim3(256), 0, s, dy, npix, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(32), 0, s, part, groups, 32LL, out);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m1, float* m2, bf16* pb, long long n, float lr, float b1, float b2,
+                float eps, int t, hipStream_t s)
+{
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m1, m2, pb, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float* delta, const float* target, long long npix, int nout, float scale, bf16* grad,
+               float* part, int groups, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mse, dim3(groups), dim3(256), 0, s, delta, target, npix, nout, scale, grad, part);
+    return hipGetLastError();
+}
+
+static dim3 pix_grid(long long npix) { return dim3((unsigned)((npix + 255) / 256)); }
+
+hipError_t pack(const State5& f, long long npix, int w, const Scales& sc, bf16* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack, pix_grid(npix), dim3(256), 0, s, f, npix, w, sc, x);
+    return hipGetLastError();
+}
+
+hipError_t pack_target(const State5& f0, const State5& f1, long long npix, const Scales& sc, float* t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_target, pix_grid(npix), dim3(256), 0, s, f0, f1, npix, sc, t);
+    return hipGetLastError();
+}
+
+hipError_t advance(const float* delta, long long npix, const Scales& sc, const State5& f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, pix_grid(npix), dim3(256), 0, s, delta, npix, sc, f);
+    return hipGetLastError();
+}
+
+hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,
+                      int groups, double* out, hipStream_t s)
+{
+    const State5 bb = b ? *b : a;
+    hipLaunchKernelGGL(k_frame_sums, dim3(groups), dim3(256), 0, s, a, bb, b != nullptr, npix, w, sc, part);
+    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(64), 0, s, part, groups, out);
+    return hipGetLastError();
+}
+
+}  // namespace sur

@@ -27,7 +27,11 @@ EXPORTED = [
     "lbm_checkpoint_load", "lbm_workspace_bytes_batch", "lbm_init_batch", "lbm_instances",
     "lbm_fields_instance", "lbm_diagnostics_instance", "lbm_tile_count", "lbm_tile_shape", "lbm_set_tile",
     "lbm_get_tile", "lbm_set_graph_steps", "lbm_set_grid", "lbm_bytes_per_update", "lbm_copy_probe",
+    "lbm_autotune", "lbm_get_grid", "lbm_reinit_fields",
 ]
+
+
+REINIT_EQUILIBRIUM, REINIT_SHIFT = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -110,6 +114,9 @@ def lib():
             L.lbm_set_graph_steps.argtypes = [vp, ip]
             L.lbm_set_grid.argtypes = [vp, ip]
             L.lbm_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
+            L.lbm_autotune.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip), C.POINTER(C.c_float)]
+            L.lbm_get_grid.argtypes = [vp]
+            L.lbm_reinit_fields.argtypes = [vp, ip, vp, vp, vp, vp, vp, ip, ip]
             L.lbm_bytes_per_update.restype = C.c_size_t
             L.lbm_bytes_per_update.argtypes = [ip]
             _lib = L
@@ -210,6 +217,14 @@ class Lattice:
         _check(rc)
         self._h = h
         self.n = n
+        # initial pressure fields, where given, by an equilibrium restart
+        for k, (_, f) in enumerate(items):
+            if f.get("p") is not None:
+                dev = {q: torch.as_tensor(np.ascontiguousarray(f[q], dtype=np.float64)).to(self.device)
+                       for q in ("phi", "ux", "uy", "T", "p")}
+                torch.cuda.current_stream(self.device).synchronize()
+                self.reinit_fields(dev, k)
+                self.stream.synchronize()
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -224,19 +239,55 @@ class Lattice:
     def step(self, n: int = 1) -> None:
         _check(self.L.lbm_step(self._h, int(n)))
 
-    def fields(self, instance: int = 0, out: str = "f64", to_host: bool = True) -> dict:
+    def fields(self, instance: int = 0, out: str = "f64", to_host: bool = True, into: dict | None = None) -> dict:
+        """Macroscopic fields phi, ux, uy, T, p of lattice `instance` as (ny, nx)
+        arrays: FP64 or FP32 (out), on the host or the device.  With `into`
+        (device tensors of the lattice's shape and the out dtype) they are
+        written there, asynchronously on the lattice's stream."""
         torch = self.torch
         ny, nx = self.shapes[instance]
         dt = torch.float64 if out == "f64" else torch.float32
-        bufs = {k: torch.empty((ny, nx), dtype=dt, device=self.device) for k in ("phi", "ux", "uy", "T", "p")}
-        _check(self.L.lbm_fields_instance(self._h, int(instance), *[C.c_void_p(bufs[k].data_ptr())
-                                                                    for k in ("phi", "ux", "uy", "T", "p")],
+        keys = ("phi", "ux", "uy", "T", "p")
+        if into is not None:
+            for k in keys:
+                a = into[k]
+                if a.dtype != dt or a.numel() != nx * ny or not a.is_contiguous() or a.device != self.device:
+                    raise ValueError("into: contiguous device tensors of the lattice's size and the out dtype")
+            bufs = into
+        else:
+            bufs = {k: torch.empty((ny, nx), dtype=dt, device=self.device) for k in keys}
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(self.L.lbm_fields_instance(self._h, int(instance), *[C.c_void_p(bufs[k].data_ptr()) for k in keys],
                                           OUT_F64 if out == "f64" else OUT_F32))
+        if into is not None:
+            return bufs
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         if to_host:
             self.stream.synchronize()
             return {k: v.cpu().numpy() for k, v in bufs.items()}
         return bufs
+
+    def reinit_fields(self, fields: dict, instance: int = 0, shift: bool = False, sync_free: bool = False) -> None:
+        """Restart of lattice `instance` from device tensors ``phi, ux, uy, T``
+        and optionally ``p``, all FP32 or all FP64, shape (ny, nx), contiguous:
+        equilibrium populations (p = 0 if absent), or, with shift, the current
+        populations shifted by the change of their equilibria (non-equilibrium
+        part kept; current p kept if absent).  The lattice's stream waits for
+        the current stream first unless sync_free (fields written on the
+        lattice's own stream)."""
+        torch = self.torch
+        keys = ("phi", "ux", "uy", "T") + (("p",) if fields.get("p") is not None else ())
+        t = [fields[k] for k in keys]
+        dt = t[0].dtype
+        ny, nx = self.shapes[instance]
+        for a in t:
+            if a.dtype != dt or a.numel() != nx * ny or not a.is_contiguous() or a.device != self.device:
+                raise ValueError("fields must be contiguous device tensors of one dtype and the lattice's size")
+        if not sync_free:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ptrs = [C.c_void_p(a.data_ptr()) for a in t] + ([None] if len(t) == 4 else [])
+        _check(self.L.lbm_reinit_fields(self._h, int(instance), *ptrs, OUT_F32 if dt == torch.float32 else OUT_F64,
+                                        REINIT_SHIFT if shift else REINIT_EQUILIBRIUM))
 
     def diagnostics(self, instance: int = 0, raise_unstable: bool = False) -> dict:
         d = Diag()
@@ -292,6 +343,40 @@ class Lattice:
 
     def set_grid(self, workgroups: int) -> None:
         _check(self.L.lbm_set_grid(self._h, int(workgroups)))
+
+    def grid(self) -> int:
+        return self.L.lbm_get_grid(self._h)
+
+    def autotune(self, steps_per_trial: int = 50, cache: str | None = None) -> dict:
+        """Chooses the tile shape (and the persistent grid of a batched lattice)
+        by timing each candidate on the live state (trial steps are ordinary
+        steps).  With ``cache`` (a JSON file), a choice stored for the same
+        precision and lattice sizes is reused instead of timing again."""
+        import json
+        key = f"p{self.precision}:" + ",".join(f"{nx}x{ny}" for ny, nx in self.shapes)
+        if len(key) > 200:
+            import hashlib
+            key = f"p{self.precision}:n{self.n}:" + hashlib.sha1(key.encode()).hexdigest()[:16]
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+            if key in table:
+                self.set_tile(table[key]["tile"])
+                self.set_grid(table[key]["grid"])
+                return dict(table[key], cached=True)
+        t, g, ms = C.c_int(0), C.c_int(0), C.c_float(0)
+        _check(self.L.lbm_autotune(self._h, int(steps_per_trial), C.byref(t), C.byref(g), C.byref(ms)))
+        res = {"tile": t.value, "grid": g.value, "ms_per_step": ms.value, "shape": tile_shapes()[t.value]}
+        if cache:
+            table[key] = res
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1)
+            os.replace(tmp, cache)
+        return dict(res, cached=False)
 
     def synchronize(self) -> None:
         self.stream.synchronize()

@@ -1,0 +1,579 @@
+"""Learned surrogate of the lattice update: a residual network of 3x3
+convolutions that advances the macroscopic state of a thermocapillary
+droplet-migration lattice by K lattice time steps at once, with the lattice
+Boltzmann update as its fallback and as the judge of its error.  Not part of
+the paper's method; built beside it.
+
+Every tensor operation of the network runs in the HIP kernels declared in
+``include/surrogate.h`` (BF16 matrix-core convolutions with FP32 accumulation,
+weight/bias gradient reductions, Adam, squared error, packing, state update,
+volume and error reductions); this module allocates buffers with PyTorch,
+marshals pointers and sequences the calls.
+
+State of a frame: five FP32 fields phi, ux, uy, T and the pressure p.  The
+pressure rides along so that a hand-back to the lattice update restarts at the
+right pressure: a restart at p = 0 emits a pressure wave that spoils the
+velocity field by tens of per cent.
+
+Network (6 convolutions, 32 channels):
+    h0 = conv(x, W0) + b0                      x: 8 channels (phi, ux/U, uy/U,
+                                               (T - T_rest)/dT, c4, c5, p/P, 0)
+    h_r = h_{r-1} + conv(relu(h_{r-1}), W_r) + b_r,   r = 1..4
+    delta = conv(relu(h_4), W5) + b5           5 used output channels
+    f_c(t + K) = f_c(t) + delta_c inc_c        (FP32 state, c = phi, ux, uy, T, p)
+Input scales per lattice: U the characteristic thermocapillary velocity,
+dT = |grad T| R, P = sigma_ref / R (the Laplace pressure), T_rest the
+conduction profile; conditioning c4 = log10(Ma) / 2, c5 = lambda_r - 1.
+Output units inc_c = kappa_c * (1, U, U, dT, P), kappa fixed from the training
+set (1 % of the rms deviation of each field from rest), so the loss weighs the
+fields by the relative error the judge measures.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+
+import numpy as np
+
+from . import lbm as _lbm
+
+CIN = (8, 32, 32, 32, 32, 32)
+N_IN = 7            # used input channels
+N_OUT = 5           # phi, ux, uy, T, p
+FIELDS = ("phi", "ux", "uy", "T", "p")
+
+_sur = None
+
+
+class SurScales(C.Structure):
+    _fields_ = [("u", C.c_float), ("dT", C.c_float), ("t_a", C.c_float), ("t_b", C.c_float), ("P", C.c_float),
+                ("c4", C.c_float), ("c5", C.c_float), ("inc", C.c_float * 5)]
+
+
+def lib():
+    global _sur
+    if _sur is None:
+        L = _lbm.lib()
+        vp, ip, i64, f = C.c_void_p, C.c_int, C.c_int64, C.c_float
+        sp = C.POINTER(SurScales)
+        pp = C.POINTER(vp)
+        L.sur_conv3x3.argtypes = [vp, ip, vp, vp, vp, vp, vp, ip, ip, ip, ip, ip, vp]
+        L.sur_adjoint_weights.argtypes = [vp, ip, vp, vp]
+        L.sur_weight_grad.argtypes = [vp, vp, ip, ip, ip, ip, ip, vp, ip, vp, vp]
+        L.sur_wgrad_scratch_floats.restype = C.c_size_t
+        L.sur_wgrad_scratch_floats.argtypes = [ip, ip]
+        L.sur_bias_grad.argtypes = [vp, i64, vp, ip, vp, vp]
+        L.sur_adam.argtypes = [vp, vp, vp, vp, vp, i64, f, f, f, f, ip, vp]
+        L.sur_mse.argtypes = [vp, vp, i64, ip, f, vp, vp, ip, vp]
+        L.sur_pack.argtypes = [pp, ip, ip, sp, vp, vp]
+        L.sur_pack_target.argtypes = [pp, pp, i64, sp, vp, vp]
+        L.sur_advance.argtypes = [vp, i64, sp, pp, vp]
+        L.sur_light_volume.argtypes = [vp, ip, ip, vp, ip, vp, vp]
+        L.sur_judge.argtypes = [pp, pp, ip, ip, sp, vp, ip, vp, vp]
+        L.sur_last_error.restype = C.c_char_p
+        _sur = L
+    return _sur
+
+
+def _ck(rc):
+    if rc != 0:
+        raise RuntimeError(f"surrogate kernel error {rc}: {lib().sur_last_error().decode()}")
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _s(stream):
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _state(f):
+    return (C.c_void_p * 5)(*[f[k].data_ptr() for k in FIELDS])
+
+
+# ---- thin wrappers with the names of the C ABI -----------------------------
+
+def sur_conv3x3(x, cin, w, bias, res, mask, out, relu_in, stream):
+    n, h, wd = x.shape[0], x.shape[1], x.shape[2]
+    _ck(lib().sur_conv3x3(_p(x), cin, _p(w), _p(bias), _p(res), _p(mask), _p(out), int(out.element_size() == 4),
+                          int(relu_in), n, h, wd, _s(stream)))
+
+
+def sur_adjoint_weights(w, cin, wt, stream):
+    _ck(lib().sur_adjoint_weights(_p(w), cin, _p(wt), _s(stream)))
+
+
+def sur_weight_grad(dy, x, cin, relu_in, part, groups, out, stream):
+    n, h, wd = dy.shape[0], dy.shape[1], dy.shape[2]
+    _ck(lib().sur_weight_grad(_p(dy), _p(x), cin, int(relu_in), n, h, wd, _p(part), groups, _p(out), _s(stream)))
+
+
+def sur_bias_grad(dy, part, groups, out, stream):
+    npix = dy.numel() // 32
+    _ck(lib().sur_bias_grad(_p(dy), npix, _p(part), groups, _p(out), _s(stream)))
+
+
+def sur_adam(p, g, m1, m2, pb, lr, t, stream, b1=0.9, b2=0.999, eps=1e-8):
+    _ck(lib().sur_adam(_p(p), _p(g), _p(m1), _p(m2), _p(pb), p.numel(), lr, b1, b2, eps, int(t), _s(stream)))
+
+
+def sur_mse(delta, target, scale, grad, part, stream):
+    nout = target.shape[-1]
+    npix = target.numel() // nout
+    _ck(lib().sur_mse(_p(delta), _p(target), npix, nout, scale, _p(grad), _p(part), part.numel(), _s(stream)))
+
+
+def sur_pack(f, sc: SurScales, x, stream):
+    h, w = f["phi"].shape
+    _ck(lib().sur_pack(_state(f), h, w, C.byref(sc), _p(x), _s(stream)))
+
+
+def sur_pack_target(f0, f1, sc: SurScales, t, stream):
+    _ck(lib().sur_pack_target(_state(f0), _state(f1), f0["phi"].numel(), C.byref(sc), _p(t), _s(stream)))
+
+
+def sur_advance(delta, sc: SurScales, f, stream):
+    _ck(lib().sur_advance(_p(delta), f["phi"].numel(), C.byref(sc), _state(f), _s(stream)))
+
+
+def sur_light_volume(phi, part, out, stream):
+    h, w = phi.shape
+    _ck(lib().sur_light_volume(_p(phi), h, w, _p(part), part.numel() // 8, _p(out), _s(stream)))
+
+
+def sur_judge(a, b, sc: SurScales, part, out, stream):
+    h, w = a["phi"].shape
+    _ck(lib().sur_judge(_state(a), _state(b), h, w, C.byref(sc), _p(part), part.numel() // 8, _p(out), _s(stream)))
+
+
+# ---- scaling of a lattice's state -----------------------------------------
+
+KAPPA_UNIT = (1.0, 1.0, 1.0, 1.0, 1.0)
+
+
+def scales_of(cfg: dict, kappa=KAPPA_UNIT) -> SurScales:
+    """Scales of a droplet-migration lattice (periodic in x, walls in y at
+    T = 0 and gradT * ny)."""
+    m = cfg["meta"]
+    U = float(m["U"])
+    R = float(m["R"])
+    gradT = float(m["gradT"])
+    dT = gradT * R
+    Ma = float(m.get("Ma", 1.0))
+    lr = float(m.get("lambda_r", cfg["lambda_l"] / cfg["lambda_h"]))
+    P = float(cfg["sigma_ref"]) / R
+    unit = (1.0, U, U, dT, P)
+    return SurScales(U, dT, 0.5 * gradT, gradT, P, math.log10(max(Ma, 1e-3)) / 2.0, lr - 1.0,
+                     (C.c_float * 5)(*[float(k) * u for k, u in zip(kappa, unit)]))
+
+
+class Surrogate:
+    """Parameters, Adam state and work buffers of the network on one device."""
+
+    def __init__(self, device="cuda:0", seed=5, stream=None, kappa=KAPPA_UNIT):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.kappa = tuple(float(k) for k in kappa)
+        g = torch.Generator().manual_seed(seed)
+        self.W, self.Wb, self.b = [], [], []
+        for layer, cin in enumerate(CIN):
+            fan_in = 9 * (cin if layer else N_IN)
+            std = math.sqrt(2.0 / fan_in) * (0.2 if 0 < layer < 5 else (0.05 if layer == 5 else 1.0))
+            w = torch.randn((32, 9, cin), generator=g) * std
+            if layer == 0:
+                w[:, :, N_IN:] = 0.0
+            if layer == 5:
+                w[N_OUT:] = 0.0
+            w = w.to(self.device)
+            self.W.append(w.contiguous())
+            self.Wb.append(w.to(torch.bfloat16).contiguous())
+            self.b.append(torch.zeros(32, device=self.device))
+        self.step_count = 0
+        self.adam = {}
+        for name, ts in (("W", self.W), ("b", self.b)):
+            self.adam[name] = [(torch.zeros_like(t), torch.zeros_like(t)) for t in ts]
+        self.Wt = [torch.empty((32, 9, 32), dtype=torch.bfloat16, device=self.device) for _ in CIN]
+        self._buf = {}
+
+    @staticmethod
+    def n_params() -> int:
+        """Trainable parameters: N_IN used input channels in layer 0, N_OUT outputs in layer 5."""
+        return (32 * 9 * N_IN + 32) + 4 * (32 * 9 * 32 + 32) + (N_OUT * 9 * 32 + N_OUT)
+
+    @staticmethod
+    def flops_per_pixel() -> int:
+        """2 x multiply-adds of one forward pass per pixel as computed (32
+        output channels in every layer, 8 input channels in the first)."""
+        return 2 * 9 * 32 * (8 + 5 * 32)
+
+    def _get(self, name, shape, dtype):
+        t = self._buf.get(name)
+        if t is None or tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+            t = self.torch.empty(shape, dtype=dtype, device=self.device)
+            self._buf[name] = t
+        return t
+
+    # ---- network ----
+    def forward(self, x, keep: bool = False):
+        """x: BF16 [N, H, W, 8].  Returns delta (FP32 [N, H, W, 32]) and, if
+        keep, the BF16 activations h0..h4 for the backward pass."""
+        torch = self.torch
+        N, H, W, _ = x.shape
+        bf = torch.bfloat16
+        hs = []
+        h = self._get("h0", (N, H, W, 32), bf)
+        sur_conv3x3(x, 8, self.Wb[0], self.b[0], None, None, h, False, self.stream)
+        hs.append(h)
+        for r in range(1, 5):
+            hn = self._get(f"h{r}" if keep else f"hp{r % 2}", (N, H, W, 32), bf)
+            sur_conv3x3(h, 32, self.Wb[r], self.b[r], h, None, hn, True, self.stream)
+            h = hn
+            hs.append(h)
+        delta = self._get("delta", (N, H, W, 32), torch.float32)
+        sur_conv3x3(h, 32, self.Wb[5], self.b[5], None, None, delta, True, self.stream)
+        return delta, (hs if keep else None)
+
+    def _backward(self, x, hs, gd, gW, gb, wpart, bpart, groups):
+        torch = self.torch
+        N, H, W, _ = x.shape
+        sur_weight_grad(gd, hs[4], 32, True, wpart, groups, gW[5], self.stream)
+        sur_bias_grad(gd, bpart, groups, gb[5], self.stream)
+        sur_adjoint_weights(self.Wb[5], 32, self.Wt[5], self.stream)
+        gh = self._get("gh0", (N, H, W, 32), torch.bfloat16)
+        sur_conv3x3(gd, 32, self.Wt[5], None, None, hs[4], gh, False, self.stream)
+        for r in range(4, 0, -1):
+            sur_weight_grad(gh, hs[r - 1], 32, True, wpart, groups, gW[r], self.stream)
+            sur_bias_grad(gh, bpart, groups, gb[r], self.stream)
+            sur_adjoint_weights(self.Wb[r], 32, self.Wt[r], self.stream)
+            gn = self._get(f"gh{r % 2 + 1}", (N, H, W, 32), torch.bfloat16)
+            sur_conv3x3(gh, 32, self.Wt[r], None, gh, hs[r - 1], gn, False, self.stream)
+            gh = gn
+        sur_weight_grad(gh, x, 8, False, wpart, groups, gW[0], self.stream)
+        sur_bias_grad(gh, bpart, groups, gb[0], self.stream)
+
+    def train_step(self, x, target, lr: float, groups: int = 256) -> float:
+        """One Adam step on the mean squared error of delta[..., :N_OUT]
+        against the target increment (FP32 [N, H, W, N_OUT], in units of inc).
+        Returns the mean squared error before the step."""
+        torch = self.torch
+        N, H, W, _ = x.shape
+        npix = N * H * W
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        delta, hs = self.forward(x, keep=True)
+        gd = self._get("gd", (N, H, W, 32), torch.bfloat16)
+        part = self._get("mse_part", (256,), torch.float32)
+        sur_mse(delta, target, 1.0 / (npix * N_OUT), gd, part, self.stream)
+        gW = [self._get(f"gW{i}", tuple(w.shape), torch.float32) for i, w in enumerate(self.W)]
+        gb = [self._get(f"gb{i}", (32,), torch.float32) for i in range(6)]
+        wpart = self._get("wpart", (groups * 32 * 9 * 32,), torch.float32)
+        bpart = self._get("bpart", (groups * 32,), torch.float32)
+        self._backward(x, hs, gd, gW, gb, wpart, bpart, groups)
+        self.step_count += 1
+        for i in range(6):
+            m1, m2 = self.adam["W"][i]
+            sur_adam(self.W[i], gW[i], m1, m2, self.Wb[i], lr, self.step_count, self.stream)
+            m1, m2 = self.adam["b"][i]
+            bb = self._get(f"bb{i}", (32,), torch.bfloat16)
+            sur_adam(self.b[i], gb[i], m1, m2, bb, lr, self.step_count, self.stream)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return float(part.sum().item()) / (npix * N_OUT)
+
+    def gradients(self, x, target, groups: int = 64):
+        """Loss (sum of squares over the N_OUT channels) and gradients, without
+        an update (for checks)."""
+        torch = self.torch
+        N, H, W, _ = x.shape
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        delta, hs = self.forward(x, keep=True)
+        gd = self._get("gd", (N, H, W, 32), torch.bfloat16)
+        part = self._get("mse_part", (256,), torch.float32)
+        sur_mse(delta, target, 1.0, gd, part, self.stream)
+        gW = [torch.empty_like(w) for w in self.W]
+        gb = [torch.empty(32, device=self.device) for _ in range(6)]
+        wpart = torch.empty(groups * 32 * 9 * 32, device=self.device)
+        bpart = torch.empty(groups * 32, device=self.device)
+        self._backward(x, hs, gd, gW, gb, wpart, bpart, groups)
+        self.stream.synchronize()
+        return float(part.sum().item()), gW, gb, delta
+
+    def state_dict(self) -> dict:
+        out = {f"W{i}": self.W[i].cpu().numpy() for i in range(6)}
+        out.update({f"b{i}": self.b[i].cpu().numpy() for i in range(6)})
+        out["kappa"] = np.asarray(self.kappa, np.float64)
+        return out
+
+    def load_state_dict(self, sd: dict) -> None:
+        torch = self.torch
+        for i in range(6):
+            self.W[i].copy_(torch.as_tensor(np.asarray(sd[f"W{i}"], np.float32)).to(self.device))
+            self.Wb[i].copy_(self.W[i].to(torch.bfloat16))
+            self.b[i].copy_(torch.as_tensor(np.asarray(sd[f"b{i}"], np.float32)).to(self.device))
+        self.kappa = tuple(float(k) for k in np.asarray(sd["kappa"]).reshape(-1))
+
+    def save(self, path: str) -> None:
+        np.savez(path, **self.state_dict())
+
+    @classmethod
+    def load(cls, path: str, device="cuda:0", stream=None) -> "Surrogate":
+        with np.load(path, allow_pickle=False) as z:
+            sd = {k: z[k] for k in z.files}
+        net = cls(device=device, stream=stream)
+        net.load_state_dict(sd)
+        return net
+
+    # ---- one block of K lattice steps on a state ----
+    def advance(self, state: dict, sc: SurScales) -> None:
+        """state (five FP32 (ny, nx) device tensors) += the predicted increment,
+        on self.stream."""
+        ny, nx = state["phi"].shape
+        x = self._get("x1", (1, ny, nx, 8), self.torch.bfloat16)
+        sur_pack(state, sc, x, self.stream)
+        delta, _ = self.forward(x)
+        sur_advance(delta, sc, state, self.stream)
+
+
+# ---- data from the lattice Boltzmann update --------------------------------
+
+def generate_pairs(items, K: int, starts, device="cuda:0"):
+    """Runs the batched FP32 lattice update over `items` (all of one size) and
+    returns network inputs X (BF16 [P, H, W, 8]) and target increments Y (FP32
+    [P, H, W, N_OUT], in units of (1, U, U, dT, P)) of the states K steps
+    later, for every start time in `starts` and every lattice."""
+    import torch
+    lat = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    ny, nx = lat.shapes[0]
+    n = len(items)
+    P = n * len(starts)
+    X = torch.empty((P, ny, nx, 8), dtype=torch.bfloat16, device=device)
+    Y = torch.empty((P, ny, nx, N_OUT), dtype=torch.float32, device=device)
+    sc = [scales_of(c) for c, _ in items]
+    st = lat.stream
+    f0 = [{k: torch.empty((ny, nx), device=device) for k in FIELDS} for _ in range(n)]
+    f1 = {k: torch.empty((ny, nx), device=device) for k in FIELDS}
+    t = 0
+    for q, s in enumerate(sorted(starts)):
+        if s < t:
+            raise ValueError("start times must be at least K apart")
+        lat.step(s - t)
+        for k in range(n):
+            lat.fields(k, out="f32", into=f0[k])
+            sur_pack(f0[k], sc[k], X[q * n + k], st)
+        lat.step(K)
+        t = s + K
+        for k in range(n):
+            lat.fields(k, out="f32", into=f1)
+            sur_pack_target(f0[k], f1, sc[k], Y[q * n + k], st)
+    st.synchronize()
+    lat.close()
+    return X, Y
+
+
+def dataset_kappa(X, frac: float = 0.01) -> tuple:
+    """kappa_c = frac x the rms deviation from rest of field c over the inputs
+    X (scaled units: phi - 1, u / U, (T - T_rest) / dT, p / P)."""
+    import torch
+
+    def ms(a):
+        return float(torch.mean(a.float() ** 2).item())
+    k_u = math.sqrt(0.5 * (ms(X[..., 1]) + ms(X[..., 2])))
+    return tuple(frac * v for v in (math.sqrt(ms(X[..., 0] - 1.0)), k_u, k_u, math.sqrt(ms(X[..., 3])),
+                                    math.sqrt(ms(X[..., 6]))))
+
+
+def train(net: Surrogate, X, Y, iters: int, batch: int, lr: float = 1e-3, seed: int = 5, log_every: int = 0,
+          crop_rows: int | None = None):
+    """Adam on random mini-batches (optionally random bands of crop_rows
+    rows at full width, since frames are periodic in x) with a cosine
+    learning-rate decay.  Returns the loss history."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    P, H = X.shape[0], X.shape[1]
+    hist = []
+    for it in range(iters):
+        idx = torch.randint(0, P, (batch,), generator=g).to(X.device)
+        xb = X.index_select(0, idx)
+        yb = Y.index_select(0, idx)
+        if crop_rows is not None and crop_rows < H:
+            y0 = int(torch.randint(0, H - crop_rows + 1, (1,), generator=g))
+            xb, yb = xb[:, y0:y0 + crop_rows], yb[:, y0:y0 + crop_rows]
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / max(1, iters)))
+        loss = net.train_step(xb.contiguous(), yb.contiguous(), lr_t)
+        hist.append(loss)
+        if log_every and (it % log_every == 0 or it == iters - 1):
+            print(f"[train] iter {it} loss {loss:.4e}", flush=True)
+    return hist
+
+
+# ---- rollout with the lattice update as fallback and judge -----------------
+
+class Hybrid:
+    """Advances one FP32 lattice by blocks of K steps: the network takes the
+    blocks, the lattice update takes every `check_every`-th block as the judge
+    (started from the network's state by a shift restart that keeps the
+    populations' non-equilibrium part) and continues from its own result.  A
+    judged one-block error (relative L2 of phi, ux, uy or T against the lattice
+    update, on deviations from rest) above `tol_check`, or a light-phase volume
+    drift above `tol_vol` since the start, hands the next `fallback_blocks`
+    blocks to the lattice update."""
+
+    def __init__(self, net: Surrogate, lat, cfg: dict, K: int = 100, check_every: int = 10,
+                 tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None):
+        import torch
+        if net.stream is not lat.stream:
+            raise ValueError("the network must run on the lattice's stream")
+        if check_every < 1:
+            raise ValueError("check_every must be >= 1")
+        self.net, self.lat, self.K = net, lat, int(K)
+        self.C = int(check_every)
+        self.tol_check, self.tol_vol = float(tol_check), float(tol_vol)
+        self.fallback_blocks = self.C if fallback_blocks is None else int(fallback_blocks)
+        self.sc = scales_of(cfg, net.kappa)
+        ny, nx = lat.shapes[0]
+        dev = lat.device
+        self.s = {k: torch.empty((ny, nx), device=dev) for k in FIELDS}
+        self.s_lbm = {k: torch.empty((ny, nx), device=dev) for k in FIELDS}
+        self.part = torch.empty(8 * 256, dtype=torch.float64, device=dev)
+        self.vol = torch.zeros(self.C + 1, dtype=torch.float64, device=dev)
+        self.judge_out = torch.empty(8, dtype=torch.float64, device=dev)
+        lat.set_graph_steps(self.K)
+        lat.fields(0, out="f32", into=self.s)
+        sur_light_volume(self.s["phi"], self.part, self.vol[self.C:], lat.stream)
+        lat.stream.synchronize()
+        self.vol0 = float(self.vol[self.C].item())
+        self.stats = dict(blocks=0, net_blocks=0, lbm_blocks=0, judged=0, fallbacks=0, max_judge=0.0,
+                          max_drift=0.0, judge_errors=[])
+
+    def run(self, blocks: int) -> dict:
+        st = self.lat.stream
+        lat_current = True      # the lattice holds self.s
+        b = 0
+        fallback_left = 0
+        while b < blocks:
+            if fallback_left > 0:
+                if not lat_current:
+                    self.lat.reinit_fields(self.s, shift=True, sync_free=True)
+                self.lat.step(self.K)
+                self.lat.fields(0, out="f32", into=self.s)
+                lat_current = True
+                self.stats["lbm_blocks"] += 1
+                fallback_left -= 1
+                b += 1
+                continue
+            n_net = min(self.C - 1, blocks - b - 1)
+            for i in range(n_net):
+                self.net.advance(self.s, self.sc)
+                sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
+                lat_current = False
+            b += n_net
+            # judge block: the network and the lattice update from one state
+            if not lat_current:
+                self.lat.reinit_fields(self.s, shift=True, sync_free=True)
+            self.net.advance(self.s, self.sc)
+            self.lat.step(self.K)
+            self.lat.fields(0, out="f32", into=self.s_lbm)
+            sur_judge(self.s, self.s_lbm, self.sc, self.part, self.judge_out, st)
+            self.s, self.s_lbm = self.s_lbm, self.s
+            lat_current = True
+            self.stats["lbm_blocks"] += 1
+            self.stats["judged"] += 1
+            b += 1
+            st.synchronize()
+            j = self.judge_out.cpu().numpy()
+            err = [math.sqrt(j[2 * c] / j[2 * c + 1]) if j[2 * c + 1] > 0 else math.sqrt(j[2 * c]) for c in range(4)]
+            self.stats["judge_errors"].append(err)
+            drift = 0.0
+            if n_net:
+                vols = self.vol[:n_net].cpu().numpy()
+                drift = float(np.max(np.abs(vols - self.vol0)) / self.vol0)
+            self.stats["max_judge"] = max(self.stats["max_judge"], max(err))
+            self.stats["max_drift"] = max(self.stats["max_drift"], drift)
+            if not (max(err) <= self.tol_check and drift <= self.tol_vol):     # NaN fails too
+                self.stats["fallbacks"] += 1
+                fallback_left = self.fallback_blocks
+        self.stats["blocks"] += blocks
+        self.stats["net_blocks"] = self.stats["blocks"] - self.stats["lbm_blocks"]
+        st.synchronize()
+        return self.stats
+
+
+def rel_err(a: dict, b: dict, cfg: dict) -> dict:
+    """Relative L2 error of fields a against b, each on the deviation of b
+    from rest (phi = 1, u = 0, T = conduction profile)."""
+    import torch
+    gradT = float(cfg["meta"]["gradT"])
+    ny = b["phi"].shape[0]
+    y = torch.arange(ny, dtype=torch.float64, device=b["phi"].device).unsqueeze(1)
+    rest = {"phi": 1.0, "ux": 0.0, "uy": 0.0, "T": gradT * (y + 0.5)}
+    out = {}
+    for k in ("phi", "ux", "uy", "T"):
+        bb = b[k].double()
+        d = (a[k].double() - bb).norm().item()
+        r = (bb - rest[k]).norm().item()
+        out[k] = d / r if r > 0 else d
+    return out
+
+
+def evaluate(net: Surrogate, items, warm: int, blocks: int, K: int = 100, check_every: int = 10,
+             tol_check: float = 0.01, device="cuda:0", log=print) -> list[dict]:
+    """For each lattice: warm it up with the lattice update, then advance it
+    `blocks` blocks of K steps (a) by the plain FP32 lattice update (the
+    reference, timed), (b) by the hybrid (timed), (c) by the network alone and
+    (d) not at all (persistence); report the errors of (b)-(d) against (a) and
+    the speedup of (b) over (a)."""
+    import torch
+    out = []
+    for cfg, f0 in items:
+        ref = _lbm.Lattice(cfg, f0, _lbm.FP32_DEV, device=device)
+        ref.set_graph_steps(K)
+        ref.step(warm)
+        snap = ref.get_state(0)
+        start = ref.fields(0, out="f32", to_host=False)
+        start = {k: v.clone() for k, v in start.items()}
+        ref.step(K)                      # graph capture outside the timed region
+        ref.set_state(0, **snap)
+        ref.synchronize()
+        t0 = time.perf_counter()
+        ref.step(blocks * K)
+        ref.synchronize()
+        t_ref = time.perf_counter() - t0
+        fr = ref.fields(0, out="f32", to_host=False)
+
+        hyb = _lbm.Lattice(cfg, f0, _lbm.FP32_DEV, device=device)
+        hyb.set_graph_steps(K)
+        hyb.step(K)                      # graph capture outside the timed region
+        hyb.set_state(0, **snap)
+        net.stream = hyb.stream
+        h = Hybrid(net, hyb, cfg, K=K, check_every=check_every, tol_check=tol_check)
+        warm_s = {k: v.clone() for k, v in h.s.items()}
+        torch.cuda.synchronize(hyb.device)
+        net.advance(warm_s, h.sc)        # first-call costs outside the timing
+        hyb.synchronize()
+        t0 = time.perf_counter()
+        stats = h.run(blocks)
+        t_hyb = time.perf_counter() - t0
+        e_h = rel_err(h.s, fr, cfg)
+
+        s = {k: v.clone() for k, v in start.items()}
+        torch.cuda.synchronize(hyb.device)
+        for _ in range(blocks):
+            net.advance(s, h.sc)
+        net.stream.synchronize()
+        e_n = rel_err(s, fr, cfg)
+        e_i = rel_err(start, fr, cfg)
+        r = dict(Ma=cfg["meta"]["Ma"], lambda_r=cfg["meta"]["lambda_r"], R=cfg["meta"]["R"],
+                 t_ref_ms=1e3 * t_ref, t_hybrid_ms=1e3 * t_hyb, speedup=t_ref / t_hyb,
+                 err_hybrid=e_h, err_net_only=e_n, err_persistence=e_i,
+                 **{k: v for k, v in stats.items() if k != "judge_errors"})
+        if log:
+            log(f"[eval] Ma={r['Ma']:.2f} lr={r['lambda_r']:.2f} R={r['R']:.1f} speedup {r['speedup']:.2f} "
+                f"hybrid {max(e_h.values()):.4f} net-only {max(e_n.values()):.4f} "
+                f"persistence {max(e_i.values()):.4f} fallbacks {stats['fallbacks']} "
+                f"max judge {stats['max_judge']:.4f}")
+        out.append(r)
+        ref.close()
+        hyb.close()
+    return out

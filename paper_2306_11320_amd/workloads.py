@@ -84,9 +84,13 @@ def heated_channel(lambda_ratio: float = 1.0, nx: int = 64, ny: int = 32, W: flo
 
 def droplet(Ma: float = 0.1, ratio: float = 1.0, nx: int = 256, ny: int = 1024, R: float = 32.0,
             cy: float | None = None, Re: float = 0.5, mu_h: float = 0.05, lambda_h: float = 0.5,
-            gradT: float | None = None, Ca_target: float | None = None) -> tuple[dict, dict]:
+            gradT: float | None = None, Ca_target: float | None = None,
+            laplace_p: bool = False) -> tuple[dict, dict]:
     """Light droplet of radius R in a heavy fluid, periodic in x, walls at
     j = -1/2 and ny - 1/2 held at T = 0 and T = gradT * ny, linear initial T.
+    With laplace_p the fields also carry p = (sigma_ref / R) (1 - phi) / 2, the
+    Young-Laplace jump across the interface, so that a start from them does not
+    emit the pressure wave of a start at p = 0.
     ratio scales the light phase's rho, mu, lambda and rho c_p.
     Ma = (rho c_p)_h R U / lambda_h, Re = R U / nu_h, U = -sigma_T gradT R / mu_h
     (characteristic scales of Sec. 4.2)."""
@@ -115,6 +119,8 @@ def droplet(Ma: float = 0.1, ratio: float = 1.0, nx: int = 256, ny: int = 1024, 
     phi = tanh_profile(r - R, 3.0)
     T = gradT * (j + 0.5)
     f = dict(phi=phi, ux=np.zeros_like(phi), uy=np.zeros_like(phi), T=T)
+    if laplace_p:
+        f["p"] = (sigma_ref / R) * 0.5 * (1.0 - phi)
     meta = dict(U=U, R=R, gradT=gradT, mu_r=ratio, lambda_r=ratio, Ma=Ma, Re=Re,
                 Ca=U * mu_h / sigma_ref, cx=cx, cy=cy)
     p["meta"] = meta
@@ -187,7 +193,8 @@ def sweep(n: int = 64, seed: int = 4, nx_range=(128, 256)) -> list[tuple[dict, d
     return out
 
 
-def sweep_instance(nx: int, ny: int, R: float, Ma: float, lambda_r: float) -> tuple[dict, dict]:
+def sweep_instance(nx: int, ny: int, R: float, Ma: float, lambda_r: float,
+                   laplace_p: bool = False) -> tuple[dict, dict]:
     mu, lam_h = 0.05, 0.5
     gradT = 8.0 / ny
     U = 0.5 * mu / R
@@ -204,6 +211,8 @@ def sweep_instance(nx: int, ny: int, R: float, Ma: float, lambda_r: float) -> tu
     i, j = grid(nx, ny)
     phi = tanh_profile(np.sqrt((i - cx) ** 2 + (j - cy) ** 2) - R, 3.0)
     f = dict(phi=phi, ux=np.zeros_like(phi), uy=np.zeros_like(phi), T=gradT * (j + 0.5))
+    if laplace_p:
+        f["p"] = (sigma_ref / R) * 0.5 * (1.0 - phi)
     p["meta"] = dict(U=U, R=R, Ma=Ma, lambda_r=lambda_r, gradT=gradT, cx=cx, cy=cy)
     return p, f
 

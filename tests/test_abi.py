@@ -12,7 +12,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions(header: str) -> list[str]:
     src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s+(lbm_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s+([a-z][a-z_0-9]*)\s*\(", src, flags=re.M)))
+
+
+def all_headers() -> list[str]:
+    d = os.path.join(ROOT, "include")
+    return [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith(".h")]
 
 
 def test_header_declares_the_boundary():
@@ -27,7 +32,8 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(lbm.LIB_PATH):
         pytest.fail("HIP library not built: run `python -m paper_2306_11320_amd.build`")
     L = ctypes.CDLL(lbm.LIB_PATH)
-    names = declared_functions(os.path.join(ROOT, "include", "lbm.h"))
+    names = [n for h in all_headers() for n in declared_functions(h)]
+    assert any(n.startswith("sur_") for n in names) and any(n.startswith("lbm_") for n in names)
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert set(lbm.EXPORTED) <= set(names)

@@ -144,3 +144,25 @@ def test_unstable_flag():
     assert d["unstable"] and d["n_nonfinite"] >= 1
     with pytest.raises(lbm.LbmError):
         lat.diagnostics(raise_unstable=True)
+
+
+def test_autotune_keeps_results(tmp_path):
+    """Autotuning times real steps with each tile shape and grid; the state it
+    leaves equals a plain run of the same number of steps, bitwise, and a
+    cached choice is reused."""
+    items = [wl.tiny(100, 40, seed=1), wl.tiny(70, 90, bc=wl.ALL_BCS[4], seed=2)]
+    announce("autotune")
+    a = lbm.Lattice.batch(items, lbm.FP32_DEV)
+    cache = str(tmp_path / "tiles.json")
+    res = a.autotune(steps_per_trial=2, cache=cache)
+    assert not res["cached"] and 0 <= res["tile"] < len(lbm.tile_shapes())
+    a.step(5)
+    n = a.get_state(0)["step"]
+    b = lbm.Lattice.batch(items, lbm.FP32_DEV)
+    b.step(n)
+    for k in range(2):
+        assert np.array_equal(a.get_state(k)["f"], b.get_state(k)["f"])
+        assert np.array_equal(a.get_state(k)["h"], b.get_state(k)["h"])
+    c = lbm.Lattice.batch(items, lbm.FP32_DEV)
+    res2 = c.autotune(steps_per_trial=2, cache=cache)
+    assert res2["cached"] and res2["tile"] == res["tile"] and c.tile() == res["tile"]

@@ -1,0 +1,295 @@
+"""Surrogate kernels (BF16 matrix cores, FP32 accumulation) against the FP64
+CPU reference with BF16 storage emulated (oracle/conv_ref.py).
+
+State-side kernels (packing, increments, state update, volume and judge
+reductions) are checked against their definitions in NumPy, and the hybrid
+rollout's bookkeeping against the plain lattice update.
+
+Tolerances: FP32 outputs within 2e-5 relative (max error over max magnitude)
+-- FP32 accumulation of <= 288 products per output, or of sums over <= 1e4
+pixels for gradients; BF16 outputs within one BF16 step (2^-7 relative) of the
+reference rounded to BF16; whole-network gradients within 3e-2 relative L2 per
+layer, since an FP32-versus-FP64 difference can flip the BF16 rounding of an
+intermediate activation.
+"""
+import numpy as np
+import pytest
+
+from oracle import conv_ref as cr
+from tests.conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sur = pytest.importorskip("paper_2306_11320_amd.surrogate")
+
+
+def t_bf16(a, dev="cuda"):
+    return torch.tensor(np.asarray(a, np.float32), device=dev).to(torch.bfloat16).contiguous()
+
+
+def t_f32(a, dev="cuda"):
+    return torch.tensor(np.asarray(a, np.float32), device=dev).contiguous()
+
+
+def host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def stream():
+    return torch.cuda.Stream()
+
+
+@pytest.mark.parametrize("cin", [8, 32])
+@pytest.mark.parametrize("relu_in", [False, True])
+def test_conv_forward(cin, relu_in, stream):
+    rng = np.random.default_rng(cin + relu_in)
+    N, H, W = 2, 5, 64
+    announce("conv_forward", cin, relu_in)
+    x = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
+    w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
+    b = rng.standard_normal(32).astype(np.float32)
+    res = rng.standard_normal((N, H, W, 32)).astype(np.float32)
+    out = torch.empty((N, H, W, 32), device="cuda")
+    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), t_f32(res), None, out, relu_in, stream)
+    stream.synchronize()
+    a = cr.relu(x) if relu_in else x
+    ref = cr.conv(a, w, b) + res
+    assert relmax(host(out), ref) <= 2e-5
+    # BF16 output with a mask
+    mask = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
+    outb = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
+    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), None, t_bf16(mask), outb, relu_in, stream)
+    stream.synchronize()
+    refb = cr.bf16_round(cr.conv(a, w, b) * (mask > 0))
+    got = host(outb)
+    assert np.all(np.abs(got - refb) <= 2 ** -7 * np.abs(refb) + 1e-6)
+
+
+def test_adjoint_input_gradient(stream):
+    rng = np.random.default_rng(7)
+    N, H, W = 1, 6, 32
+    announce("adjoint")
+    for cin in (8, 32):
+        w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
+        g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
+        wt = torch.empty((32, 9, 32), dtype=torch.bfloat16, device="cuda")
+        sur.sur_adjoint_weights(t_bf16(w), cin, wt, stream)
+        out = torch.empty((N, H, W, 32), device="cuda")
+        sur.sur_conv3x3(t_bf16(g), 32, wt, None, None, None, out, False, stream)
+        stream.synchronize()
+        ref = cr.conv_input_grad(g, w)
+        got = host(out)[..., :cin]
+        assert relmax(got, ref) <= 2e-5
+        if cin < 32:
+            assert np.abs(host(out)[..., cin:]).max() == 0.0
+
+
+@pytest.mark.parametrize("cin", [8, 32])
+def test_weight_and_bias_gradient(cin, stream):
+    rng = np.random.default_rng(11 + cin)
+    N, H, W = 2, 7, 96
+    announce("wgrad", cin)
+    a = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
+    g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
+    for relu_in in (False, True):
+        groups = 13
+        part = torch.empty(groups * 32 * 9 * cin, device="cuda")
+        out = torch.empty((32, 9, cin), device="cuda")
+        sur.sur_weight_grad(t_bf16(g), t_bf16(a), cin, relu_in, part, groups, out, stream)
+        stream.synchronize()
+        ref = cr.conv_weight_grad(g, cr.relu(a) if relu_in else a)
+        assert relmax(host(out), ref) <= 2e-5
+    bpart = torch.empty(5 * 32, device="cuda")
+    bout = torch.empty(32, device="cuda")
+    sur.sur_bias_grad(t_bf16(g), bpart, 5, bout, stream)
+    stream.synchronize()
+    assert relmax(host(bout), g.sum(axis=(0, 1, 2))) <= 2e-5
+
+
+def test_adam_and_mse(stream):
+    rng = np.random.default_rng(3)
+    announce("adam_mse")
+    p = rng.standard_normal(1000)
+    gr = rng.standard_normal(1000)
+    m1 = np.zeros(1000)
+    m2 = np.zeros(1000)
+    tp, tg, tm1, tm2 = t_f32(p), t_f32(gr), t_f32(m1), t_f32(m2)
+    pb = torch.empty(1000, dtype=torch.bfloat16, device="cuda")
+    for t in (1, 2, 3):
+        sur.sur_adam(tp, tg, tm1, tm2, pb, 1e-2, t, stream)
+        p, m1, m2 = cr.adam(p, gr, m1, m2, t, lr=1e-2)
+    stream.synchronize()
+    assert relmax(host(tp), p) <= 1e-6
+    assert np.array_equal(host(pb), cr.bf16_round(host(tp)))
+    N, H, W = 1, 3, 32
+    d = rng.standard_normal((N, H, W, 32)).astype(np.float32)
+    tg4 = rng.standard_normal((N, H, W, 4)).astype(np.float32)
+    grad = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
+    part = torch.empty(7, device="cuda")
+    sur.sur_mse(t_f32(d), t_f32(tg4), 0.25, grad, part, stream)
+    stream.synchronize()
+    e = d[..., :4].astype(np.float64) - tg4
+    assert abs(float(part.sum()) - np.sum(e * e)) <= 1e-5 * np.sum(e * e)
+    gref = np.zeros((N, H, W, 32))
+    gref[..., :4] = 0.5 * e
+    assert np.all(np.abs(host(grad) - cr.bf16_round(gref)) <= 2 ** -7 * np.abs(gref) + 1e-7)
+
+
+def test_network_gradients_vs_reference():
+    announce("network_gradients")
+    net = sur.Surrogate(seed=3)
+    rng = np.random.default_rng(5)
+    N, H, W = 2, 6, 64
+    x = np.zeros((N, H, W, 8))
+    x[..., :6] = rng.standard_normal((N, H, W, 6))
+    x = cr.bf16_round(x)
+    target = rng.standard_normal((N, H, W, 4)).astype(np.float32)
+    loss, gW, gb, delta = net.gradients(t_bf16(x), t_f32(target))
+    ref = cr.NetRef([w.cpu().numpy() for w in net.W], [b.cpu().numpy() for b in net.b])
+    rloss, rgW, rgb, rdelta = ref.loss_and_grads(x, target.astype(np.float64), 1.0)
+    assert abs(loss - rloss) <= 1e-3 * rloss
+    assert relmax(host(delta)[..., :4], rdelta[..., :4]) <= 2e-2
+    for i in range(6):
+        g, r = host(gW[i]), rgW[i]
+        e = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        assert e <= 3e-2, (i, e)
+        e = np.linalg.norm(host(gb[i]) - rgb[i]) / max(np.linalg.norm(rgb[i]), 1e-30)
+        assert e <= 3e-2, (i, "bias", e)
+
+
+def test_training_fits_a_shift():
+    """The GPU training loop learns a fixed map: the state shifted by one node
+    in x (a pure transport over K steps), with the loss falling 10x."""
+    announce("training_fits_shift")
+    net = sur.Surrogate(seed=1)
+    rng = np.random.default_rng(2)
+    P, H, W = 32, 8, 64
+    x = np.zeros((P, H, W, 8))
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for p in range(P):
+        k = rng.integers(1, 4)
+        ph = rng.uniform(0, 6.28)
+        x[p, :, :, 0] = np.sin(2 * np.pi * k * xx / W + ph) * np.cos(np.pi * yy / H)
+        x[p, :, :, 1] = 0.5 * np.cos(2 * np.pi * k * xx / W + ph)
+    x = cr.bf16_round(x)
+    y = (np.roll(x[..., :4], 1, axis=2) - x[..., :4]).astype(np.float32)
+    X, Y = t_bf16(x), t_f32(y)
+    hist = sur.train(net, X, Y, iters=300, batch=8, lr=3e-3, seed=0)
+    assert np.mean(hist[-20:]) < 0.1 * np.mean(hist[:5]), (hist[:5], hist[-5:])
+
+
+# ---- state-side kernels ------------------------------------------------------
+
+def _cfg_scales():
+    from paper_2306_11320_amd import workloads as wl
+    cfg, _ = wl.sweep_instance(64, 256, 12.0, 3.0, 1.5)
+    return cfg
+
+
+def _rand_state(rng, h, w):
+    return {k: torch.tensor(rng.standard_normal((h, w)).astype(np.float32), device="cuda").contiguous()
+            for k in sur.FIELDS}
+
+
+def test_pack_target_and_advance(stream):
+    """sur_pack against its definition (BF16 rounding of the scaled fields);
+    sur_advance(sur_pack_target(f0, f1)) takes f0 to f1 within FP32 rounding."""
+    announce("pack_target_advance")
+    rng = np.random.default_rng(21)
+    cfg = _cfg_scales()
+    sc = sur.scales_of(cfg, (0.01, 0.02, 0.03, 0.04, 0.05))
+    h, w = 9, 64
+    f0, f1 = _rand_state(rng, h, w), _rand_state(rng, h, w)
+    x = torch.empty((h, w, 8), dtype=torch.bfloat16, device="cuda")
+    sur.sur_pack(f0, sc, x, stream)
+    t = torch.empty((h, w, 5), device="cuda")
+    sur.sur_pack_target(f0, f1, sc, t, stream)
+    stream.synchronize()
+    H = {k: v.cpu().numpy().astype(np.float64) for k, v in f0.items()}
+    y = np.arange(h, dtype=np.float64)[:, None]
+    want = np.zeros((h, w, 8))
+    want[..., 0] = H["phi"]
+    want[..., 1] = H["ux"] / sc.u
+    want[..., 2] = H["uy"] / sc.u
+    want[..., 3] = (H["T"] - (sc.t_a + sc.t_b * y)) / sc.dT
+    want[..., 4] = sc.c4
+    want[..., 5] = sc.c5
+    want[..., 6] = H["p"] / sc.P
+    got = host(x)
+    assert np.all(np.abs(got - cr.bf16_round(want)) <= 2 ** -8 * np.abs(want) + 1e-30)
+    inc = np.array([sc.inc[c] for c in range(5)])
+    tt = host(t)
+    for c, k in enumerate(sur.FIELDS):
+        d = (f1[k].double() - f0[k].double()).cpu().numpy() / inc[c]
+        assert np.allclose(tt[..., c], d, rtol=2e-6, atol=1e-6 / inc[c])
+    delta = torch.zeros((h, w, 32), device="cuda")
+    delta[..., :5] = t
+    g = {k: v.clone() for k, v in f0.items()}
+    torch.cuda.synchronize()
+    sur.sur_advance(delta, sc, g, stream)
+    stream.synchronize()
+    for k in sur.FIELDS:
+        assert torch.allclose(g[k], f1[k], rtol=1e-5, atol=1e-5), k
+
+
+def test_light_volume_and_judge(stream):
+    announce("volume_judge")
+    rng = np.random.default_rng(22)
+    cfg = _cfg_scales()
+    sc = sur.scales_of(cfg)
+    h, w = 37, 64
+    a, b = _rand_state(rng, h, w), _rand_state(rng, h, w)
+    part = torch.empty(8 * 13, dtype=torch.float64, device="cuda")
+    out = torch.empty(8, dtype=torch.float64, device="cuda")
+    sur.sur_light_volume(a["phi"], part, out[:1], stream)
+    stream.synchronize()
+    phi = a["phi"].double().cpu().numpy()
+    assert abs(float(out[0]) - np.sum(0.5 * (1 - phi))) <= 1e-12 * np.sum(np.abs(phi)) * 10
+    sur.sur_judge(a, b, sc, part, out, stream)
+    stream.synchronize()
+    A = {k: v.double().cpu().numpy() for k, v in a.items()}
+    B = {k: v.double().cpu().numpy() for k, v in b.items()}
+    y = np.arange(h, dtype=np.float64)[:, None]
+    rest = {"phi": 1.0, "ux": 0.0, "uy": 0.0, "T": float(sc.t_a) + float(sc.t_b) * y}
+    o = out.cpu().numpy()
+    for c, k in enumerate(("phi", "ux", "uy", "T")):
+        assert np.isclose(o[2 * c], np.sum((A[k] - B[k]) ** 2), rtol=1e-12)
+        assert np.isclose(o[2 * c + 1], np.sum((B[k] - rest[k]) ** 2), rtol=1e-12)
+
+
+def test_hybrid_judging_every_block_is_the_lattice_update():
+    """With the judge on every block the hybrid's state is the lattice
+    update's own (bitwise); with a huge tolerance an untrained network runs
+    undisturbed; with a tiny one every judged block falls back."""
+    from paper_2306_11320_amd import lbm, workloads as wl
+    announce("hybrid_bookkeeping")
+    cfg, f0 = wl.sweep_instance(64, 256, 12.0, 3.0, 1.5, laplace_p=True)
+    ref = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    ref.step(300)
+    fr = ref.fields(0, out="f32", to_host=False)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    net = sur.Surrogate(seed=2, stream=lat.stream)
+    h = sur.Hybrid(net, lat, cfg, K=100, check_every=1, tol_check=1e9, tol_vol=1e9)
+    st = h.run(3)
+    assert st["lbm_blocks"] == 3 and st["net_blocks"] == 0 and st["judged"] == 3
+    for k in sur.FIELDS:
+        assert torch.equal(h.s[k], fr[k]), k
+    lat2 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    net.stream = lat2.stream
+    h2 = sur.Hybrid(net, lat2, cfg, K=100, check_every=4, tol_check=1e9, tol_vol=1e9)
+    st2 = h2.run(8)
+    assert (st2["net_blocks"], st2["lbm_blocks"], st2["fallbacks"]) == (6, 2, 0)
+    lat3 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    net.stream = lat3.stream
+    h3 = sur.Hybrid(net, lat3, cfg, K=100, check_every=4, tol_check=0.0, fallback_blocks=2)
+    st3 = h3.run(10)
+    # 3 network + 1 judged, 2 fallback, 3 network + 1 judged -> 10 blocks
+    assert (st3["net_blocks"], st3["lbm_blocks"], st3["fallbacks"]) == (6, 4, 2)
+    for L in (ref, lat, lat2, lat3):
+        L.close()
