@@ -1,12 +1,16 @@
 """Throughput of the fused lattice Boltzmann step on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload droplet|bubbles|channel|sweep] [--no-cpu]
+                    [--surrogate N]
 
 A step is one time step of the three coupled D2Q9 LBEs over the whole lattice
 (one fused kernel launch).  The default workload is the droplet-migration
 lattice, 256 x 1024 nodes, Ma = 1, density/viscosity/conductivity/heat-
 capacitance ratio 0.5, timed in FP32 deviation storage (the headline value)
-and in FP64.  Prints one JSON line.
+and in FP64.  With the droplet workload the learned surrogate is also timed
+against the plain FP32 lattice update on N fresh 256 x 1024 droplet lattices
+(sweep parameters, seed 55) over 10 blocks of 100 steps after 30000 steps of
+warm-up, with its errors.  Prints one JSON line.
 
 Only one GPU is used; --gpus above 1 is refused.
 """
@@ -147,6 +151,36 @@ def cpu_baseline(items, budget_s: float = 15.0):
                        f"{dt:.1f} s on {threads} OpenMP threads")
 
 
+def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000):
+    """Hybrid rollout of the trained surrogate against the plain FP32 lattice
+    update: speedup and relative L2 errors over `blocks` blocks of 100 steps."""
+    from paper_2306_11320_amd import surrogate as S
+    from paper_2306_11320_amd.train_surrogate import sweep_items
+    wpath = os.path.join(ROOT, "paper_2306_11320_amd", "weights", "surrogate_k100.npz")
+    net = S.Surrogate.load(wpath)
+    items = sweep_items(n, 55, 256, 1024)
+    res = S.evaluate(net, items, warm=warm, blocks=blocks, K=100, check_every=10, chunk=blocks,
+                     log=lambda m: print(m, file=sys.stderr, flush=True))
+    sp = [sum(r["t_ref_ms"]) / sum(r["t_hybrid_ms"]) for r in res]
+    err = [max(r["err_hybrid"][-1].values()) for r in res]
+    ok = [s_ for s_, e in zip(sp, err) if e <= 0.01]
+    srt = sorted(ok)
+    return {
+        "workload": "droplet_sweep_256x1024", "K": 100, "blocks": blocks, "warm_steps": warm,
+        "instances": n, "weights": "paper_2306_11320_amd/weights/surrogate_k100.npz",
+        "speedup": [round(v, 3) for v in sp],
+        "max_rel_l2": [round(v, 5) for v in err],
+        "max_rel_l2_net_only": [round(max(r["err_net_only"][-1].values()), 5) for r in res],
+        "max_rel_l2_persistence": [round(max(r["err_persistence"][-1].values()), 5) for r in res],
+        "rel_l2_by_field": [{k: round(v, 5) for k, v in r["err_hybrid"][-1].items()} for r in res],
+        "fallbacks": [r["fallbacks"] for r in res],
+        "instances_within_1pct": len(ok),
+        "speedup_at_le_1pct_median": round(srt[len(srt) // 2], 3) if srt else None,
+        "lbm_ms": [round(sum(r["t_ref_ms"]), 3) for r in res],
+        "hybrid_ms": [round(sum(r["t_hybrid_ms"]), 3) for r in res],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +190,8 @@ def main():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--surrogate", type=int, default=4, metavar="N",
+                    help="lattices for the surrogate leg (droplet workload only; 0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the plain copy kernel on MIB MiB, 20 times (counter calibration)")
     args = ap.parse_args()
@@ -223,6 +259,9 @@ def main():
                        "roofline": {"bound": "hbm", "achieved": round(a64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(a64 / HBM_PEAK_GBS, 4),
                                     "traffic": stored_traffic(args.workload, "fp64")}}
+    if args.workload == "droplet" and args.surrogate > 0:
+        print("[bench] surrogate", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_leg(args.surrogate)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(items)

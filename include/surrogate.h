@@ -27,24 +27,27 @@ extern "C" {
 #endif
 
 /* out = [mask > 0] * (conv(A, w) + bias) + res, A = max(in, 0) if relu_in else
- * in; in has cin in {8, 32} channels; out has 32 channels, FP32 if out_f32
- * else BF16.  bias, res and mask may be NULL (res has out's type; mask is BF16
- * with 32 channels). */
+ * in, conv with dilation dil (1 <= dil <= w: taps at (dy, dx) * dil); in has
+ * cin in {8, 32} channels; out has 32 channels, FP32 if out_f32 else BF16.
+ * bias, res and mask may be NULL (res has out's type; mask is BF16 with 32
+ * channels). */
 int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias, const void* d_res,
-                const void* d_mask, void* d_out, int out_f32, int relu_in, int n, int h, int w, void* stream);
+                const void* d_mask, void* d_out, int out_f32, int relu_in, int dil, int n, int h, int w,
+                void* stream);
 
 /* Weights of the adjoint (input-gradient) convolution of a layer with cin
  * input channels: wt[ci][8 - tap][co] = w[co][tap][ci], 32 x 9 x 32 BF16.
- * sur_conv3x3(dy, 32, wt, ...) then computes the gradient with respect to the
- * layer's input (periodic x, zero-padded y: the exact adjoint). */
+ * sur_conv3x3(dy, 32, wt, ...) with the layer's dilation then computes the
+ * gradient with respect to the layer's input (periodic x, zero-padded y: the
+ * exact adjoint). */
 int sur_adjoint_weights(const void* d_w, int cin, void* d_wt, void* stream);
 
-/* Weight gradient dW[co][tap][ci] = sum_p dy[p][co] A[p + offset(tap)][ci]
+/* Weight gradient dW[co][tap][ci] = sum_p dy[p][co] A[p + dil offset(tap)][ci]
  * (A = max(in, 0) if relu_in) into d_out (32*9*cin FP32), through `groups`
  * per-workgroup partial sums in d_part (sur_wgrad_scratch_floats floats),
  * summed in a fixed order. */
-int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, int n, int h, int w, float* d_part,
-                    int groups, float* d_out, void* stream);
+int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, int dil, int n, int h, int w,
+                    float* d_part, int groups, float* d_out, void* stream);
 size_t sur_wgrad_scratch_floats(int cin, int groups);
 
 /* Bias gradient db[co] = sum_p dy[p][co] (32 FP32), through 32*groups partials. */
@@ -75,7 +78,8 @@ typedef struct {
 } sur_scales;
 
 /* Network input of one frame: 8 BF16 channels (phi, ux/u, uy/u,
- * (T - T_rest(y))/dT, c4, c5, p/P, 0) into d_x (h*w*8 values). */
+ * (T - T_rest(y))/dT, c4, c5, (p - P (1 - phi)/2)/P, 0) into d_x (h*w*8
+ * values): the pressure less its Young-Laplace part. */
 int sur_pack(const float* const* d_f, int h, int w, const sur_scales* scales, void* d_x, void* stream);
 /* Target increment between states f0 and f1: (f1_c - f0_c) / inc[c] for the
  * five fields, 5 FP32 channels per pixel into d_t. */

@@ -35,6 +35,8 @@ def shifted(a: np.ndarray, dy: int, dx: int) -> np.ndarray:
     """out[n, y, x] = a[n, y + dy, (x + dx) mod W], zero where y + dy is outside."""
     out = np.zeros_like(a)
     H = a.shape[1]
+    if abs(dy) >= H:
+        return out
     rolled = np.roll(a, -dx, axis=2)
     if dy >= 0:
         out[:, :H - dy] = rolled[:, dy:]
@@ -43,37 +45,38 @@ def shifted(a: np.ndarray, dy: int, dx: int) -> np.ndarray:
     return out
 
 
-def conv(a: np.ndarray, w: np.ndarray, bias=None) -> np.ndarray:
-    """out[n, y, x, co] = sum_{t, ci} a[n, y + dy_t, x + dx_t, ci] w[co, t, ci] (+ bias[co])."""
+def conv(a: np.ndarray, w: np.ndarray, bias=None, dil: int = 1) -> np.ndarray:
+    """out[n, y, x, co] = sum_{t, ci} a[n, y + d dy_t, x + d dx_t, ci] w[co, t, ci] (+ bias[co]),
+    d the dilation."""
     a = np.asarray(a, np.float64)
     w = np.asarray(w, np.float64)
     out = np.zeros(a.shape[:3] + (w.shape[0],))
     for t, (dy, dx) in enumerate(TAPS):
-        out += shifted(a, dy, dx) @ w[:, t, :].T
+        out += shifted(a, dil * dy, dil * dx) @ w[:, t, :].T
     if bias is not None:
         out += np.asarray(bias, np.float64)
     return out
 
 
-def conv_input_grad(g: np.ndarray, w: np.ndarray) -> np.ndarray:
-    """Gradient of sum(conv(a, w) * g) with respect to a."""
+def conv_input_grad(g: np.ndarray, w: np.ndarray, dil: int = 1) -> np.ndarray:
+    """Gradient of sum(conv(a, w, dil=dil) * g) with respect to a."""
     g = np.asarray(g, np.float64)
     w = np.asarray(w, np.float64)
     out = np.zeros(g.shape[:3] + (w.shape[2],))
     for t, (dy, dx) in enumerate(TAPS):
-        out += shifted(g @ w[:, t, :], -dy, -dx)
+        out += shifted(g @ w[:, t, :], -dil * dy, -dil * dx)
     return out
 
 
-def conv_weight_grad(g: np.ndarray, a: np.ndarray) -> np.ndarray:
-    """Gradient of sum(conv(a, w) * g) with respect to w: [co, t, ci]."""
+def conv_weight_grad(g: np.ndarray, a: np.ndarray, dil: int = 1) -> np.ndarray:
+    """Gradient of sum(conv(a, w, dil=dil) * g) with respect to w: [co, t, ci]."""
     g = np.asarray(g, np.float64)
     a = np.asarray(a, np.float64)
     co, ci = g.shape[3], a.shape[3]
     out = np.zeros((co, 9, ci))
     gf = g.reshape(-1, co)
     for t, (dy, dx) in enumerate(TAPS):
-        out[:, t, :] = gf.T @ shifted(a, dy, dx).reshape(-1, ci)
+        out[:, t, :] = gf.T @ shifted(a, dil * dy, dil * dx).reshape(-1, ci)
     return out
 
 
@@ -99,19 +102,22 @@ class NetRef:
     with nout the number of target channels.
 
     Weights: W0 [32, 9, 8], W1..W4 [32, 9, 32], W5 [32, 9, 32] (rows >= nout zero);
-    biases [32].  Activations h_r are stored as BF16; delta is kept in FP32.
+    biases [32]; layer r's taps dilated by dil[r].  Activations h_r are stored
+    as BF16; delta is kept in FP32.
     """
 
-    def __init__(self, weights, biases):
+    def __init__(self, weights, biases, dil=(1, 1, 1, 1, 1, 1)):
         self.W = [bf16_round(w) for w in weights]
         self.b = [np.asarray(b, np.float64) for b in biases]
+        self.d = tuple(int(v) for v in dil)
 
     def forward(self, x):
         x = bf16_round(x)
-        hs = [bf16_round(conv(x, self.W[0], self.b[0]))]
+        d = self.d
+        hs = [bf16_round(conv(x, self.W[0], self.b[0], d[0]))]
         for r in range(1, 5):
-            hs.append(bf16_round(hs[-1] + conv(relu(hs[-1]), self.W[r], self.b[r])))
-        delta = fp32_round(conv(relu(hs[-1]), self.W[5], self.b[5]))
+            hs.append(bf16_round(hs[-1] + conv(relu(hs[-1]), self.W[r], self.b[r], d[r])))
+        delta = fp32_round(conv(relu(hs[-1]), self.W[5], self.b[5], d[5]))
         return x, hs, delta
 
     def loss_and_grads(self, x, target, scale):
@@ -124,13 +130,14 @@ class NetRef:
         gd = bf16_round(gd)
         gW = [None] * 6
         gb = [None] * 6
-        gW[5] = conv_weight_grad(gd, relu(hs[4]))
+        d = self.d
+        gW[5] = conv_weight_grad(gd, relu(hs[4]), d[5])
         gb[5] = gd.sum(axis=(0, 1, 2))
-        gh = bf16_round(conv_input_grad(gd, self.W[5]) * (hs[4] > 0))
+        gh = bf16_round(conv_input_grad(gd, self.W[5], d[5]) * (hs[4] > 0))
         for r in range(4, 0, -1):
-            gW[r] = conv_weight_grad(gh, relu(hs[r - 1]))
+            gW[r] = conv_weight_grad(gh, relu(hs[r - 1]), d[r])
             gb[r] = gh.sum(axis=(0, 1, 2))
-            gh = bf16_round(gh + conv_input_grad(gh, self.W[r]) * (hs[r - 1] > 0))
-        gW[0] = conv_weight_grad(gh, x)
+            gh = bf16_round(gh + conv_input_grad(gh, self.W[r], d[r]) * (hs[r - 1] > 0))
+        gW[0] = conv_weight_grad(gh, x, d[0])
         gb[0] = gh.sum(axis=(0, 1, 2))
         return loss, gW, gb, delta

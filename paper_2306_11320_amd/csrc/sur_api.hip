@@ -28,14 +28,15 @@ using sur::bf16;
 extern "C" {
 
 int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias, const void* d_res,
-                const void* d_mask, void* d_out, int out_f32, int relu_in, int n, int h, int w, void* stream)
+                const void* d_mask, void* d_out, int out_f32, int relu_in, int dil, int n, int h, int w, void* stream)
 {
     if (!d_in || !d_w || !d_out) return bad("sur_conv3x3: NULL tensor");
     if (cin != 8 && cin != 32) return bad("sur_conv3x3: cin must be 8 or 32");
     if (n < 1 || h < 1 || w < 32 || w % 32) return bad("sur_conv3x3: need n, h >= 1 and w a multiple of 32");
+    if (dil < 1 || dil > w) return bad("sur_conv3x3: need 1 <= dil <= w");
     if (!aligned16(d_in) || !aligned16(d_w)) return bad("sur_conv3x3: in and w must be 16-byte aligned");
     return check(sur::conv(static_cast<const bf16*>(d_in), cin, static_cast<const bf16*>(d_w), d_bias, d_res,
-                           static_cast<const bf16*>(d_mask), d_out, out_f32, relu_in, n, h, w,
+                           static_cast<const bf16*>(d_mask), d_out, out_f32, relu_in, dil, n, h, w,
                            static_cast<hipStream_t>(stream)),
                  "sur_conv3x3");
 }
@@ -51,13 +52,14 @@ int sur_adjoint_weights(const void* d_w, int cin, void* d_wt, void* stream)
 
 size_t sur_wgrad_scratch_floats(int cin, int groups) { return (size_t)groups * 32 * 9 * (size_t)cin; }
 
-int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, int n, int h, int w, float* d_part,
-                    int groups, float* d_out, void* stream)
+int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, int dil, int n, int h, int w,
+                    float* d_part, int groups, float* d_out, void* stream)
 {
     if (!d_dy || !d_in || !d_part || !d_out) return bad("sur_weight_grad: NULL tensor");
     if (cin != 8 && cin != 32) return bad("sur_weight_grad: cin must be 8 or 32");
     if (n < 1 || h < 1 || w < 32 || w % 32 || groups < 1) return bad("sur_weight_grad: bad sizes");
-    return check(sur::wgrad(static_cast<const bf16*>(d_dy), static_cast<const bf16*>(d_in), cin, relu_in, n, h, w,
+    if (dil < 1 || dil > w) return bad("sur_weight_grad: need 1 <= dil <= w");
+    return check(sur::wgrad(static_cast<const bf16*>(d_dy), static_cast<const bf16*>(d_in), cin, relu_in, dil, n, h, w,
                             d_part, groups, d_out, static_cast<hipStream_t>(stream)),
                  "sur_weight_grad");
 }

@@ -10,10 +10,10 @@ namespace sur {
 typedef __bf16 bf16;
 
 hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const void* res, const bf16* mask,
-                void* out, int out_f32, int relu_in, int N, int H, int W, hipStream_t s);
+                void* out, int out_f32, int relu_in, int dil, int N, int H, int W, hipStream_t s);
 hipError_t adjoint_weights(const bf16* w, int cin, bf16* wt, hipStream_t s);
-hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int N, int H, int W, float* part, int groups,
-                 float* out, hipStream_t s);
+hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int dil, int N, int H, int W, float* part,
+                 int groups, float* out, hipStream_t s);
 hipError_t bgrad(const bf16* dy, long long npix, float* part, int groups, float* out, hipStream_t s);
 hipError_t adam(float* p, const float* g, float* m1, float* m2, bf16* pb, long long n, float lr, float b1, float b2,
                 float eps, int t, hipStream_t s);

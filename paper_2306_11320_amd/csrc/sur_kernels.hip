@@ -37,13 +37,13 @@ __device__ inline bf16x8 relu8(bf16x8 v)
 
 __device__ inline float to_f(bf16 v) { return (float)v; }
 
-// out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + dy, x + dx, ci) W[co][tap][ci] )
-// A = relu(in) if relu_in.  Epilogue: + bias[co]; then, if mask, zero where
+// out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + d dy, x + d dx, ci) W[co][tap][ci] )
+// with dilation d; A = relu(in) if relu_in.  Epilogue: + bias[co]; then, if mask, zero where
 // mask <= 0; then, if res, + res.  The output is FP32 or BF16.
 __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, int cin, const bf16* __restrict__ w,
                                               const float* __restrict__ bias, const void* __restrict__ res,
                                               const bf16* __restrict__ mask, void* __restrict__ out, int out_f32,
-                                              int relu_in, int N, int H, int W)
+                                              int relu_in, int dil, int N, int H, int W)
 {
     const int lane = threadIdx.x % 64;
     const long long seg = (long long)blockIdx.x * 4 + threadIdx.x / 64;  // 32-pixel segment
@@ -60,9 +60,9 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, int c
         bf16x8 a = {}, b = {};
         if (kk < K) {
             const int tap = kk / cin, ci = kk % cin;
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            const int dy = (tap / 3 - 1) * dil, dx = (tap % 3 - 1) * dil;
             const int yy = y + dy;
-            int xx = x0 + m + dx;
+            int xx = x0 + m + dx;  // |dx| <= W, so one wrap suffices
             xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
             if (yy >= 0 && yy < H) {
                 a = load8(in + (((long long)n * H + yy) * W + xx) * cin + ci);
@@ -102,15 +102,15 @@ __global__ void k_adjoint_weights(const bf16* __restrict__ w, int cin, bf16* __r
 }
 
 // Weight gradient partials: part[g][co][kk] = sum over the workgroup's pixels of
-// dy[p][co] * A(p + off(tap))[ci], kk = tap * cin + ci, A = relu(in) if relu_in.
-// Each workgroup walks whole 32-pixel segments; LDS holds dy of the segment
-// and the three input rows it touches.
+// dy[p][co] * A(p + d off(tap))[ci], kk = tap * cin + ci, A = relu(in) if
+// relu_in, dilation d.  Each workgroup walks whole 32-pixel segments; LDS
+// holds dy of the segment and the nine shifted 32-pixel input windows it meets.
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, const bf16* __restrict__ in, int cin,
-                                               int relu_in, int N, int H, int W, float* __restrict__ part,
+                                               int relu_in, int dil, int N, int H, int W, float* __restrict__ part,
                                                int ntiles_n)
 {
     __shared__ bf16 sdy[32][33];          // [pixel][co] (+1 pad)
-    __shared__ bf16 sa[3][34][33];        // [row][pixel + 1][ci] (+1 pad), cin <= 32
+    __shared__ bf16 sa[9][32][33];        // [tap][pixel][ci] (+1 pad), cin <= 32
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int segs_per_row = W / 32;
     const long long nseg = (long long)N * H * segs_per_row;
@@ -126,17 +126,17 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, cons
             const int p = q / 32, c = q % 32;
             sdy[p][c] = dy[(((long long)n * H + y) * W + x0 + p) * 32 + c];
         }
-        for (int q = threadIdx.x; q < 3 * 34 * 32; q += 256) {
-            const int c = q % 32, p = (q / 32) % 34, r = q / (32 * 34);
-            const int yy = y + r - 1;
-            int xx = x0 + p - 1;
+        for (int q = threadIdx.x; q < 9 * 32 * 32; q += 256) {
+            const int c = q % 32, p = (q / 32) % 32, tap = q / (32 * 32);
+            const int yy = y + (tap / 3 - 1) * dil;
+            int xx = x0 + p + (tap % 3 - 1) * dil;
             xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
             bf16 v = (bf16)0.f;
             if (c < cin && yy >= 0 && yy < H) {
                 v = in[(((long long)n * H + yy) * W + xx) * cin + c];
                 if (relu_in && !(to_f(v) > 0.f)) v = (bf16)0.f;
             }
-            sa[r][p][c] = v;
+            sa[tap][p][c] = v;
         }
         __syncthreads();
         // GEMM: M = co (32), N = kk (tiles of 32), K = 32 pixels in two blocks of 16
@@ -148,13 +148,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, cons
                 bf16x8 a, b;
                 const int p0 = kb + 8 * (lane / 32);
                 const int kk = tile * 32 + lane % 32;
-                const int tap = kk / cin, ci = kk % cin;
                 const bool valid = kk < K;
-                const int dyy = valid ? tap / 3 : 0, dxx = valid ? tap % 3 : 0;
+                const int tap = valid ? kk / cin : 0, ci = valid ? kk % cin : 0;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     a[j] = sdy[p0 + j][lane % 32];
-                    b[j] = valid ? sa[dyy][p0 + j + dxx][ci] : (bf16)0.f;
+                    b[j] = valid ? sa[tap][p0 + j][ci] : (bf16)0.f;
                 }
                 acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
             }
@@ -249,7 +248,9 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ delta /*C
 }
 
 // Network input from the five FP32 state fields of one frame (x fastest):
-// channels (phi, ux / U, uy / U, (T - T_rest(y)) / dT, c4, c5, p / P, 0), BF16.
+// channels (phi, ux / U, uy / U, (T - T_rest(y)) / dT, c4, c5,
+// (p - P (1 - phi) / 2) / P, 0), BF16: the pressure enters less its
+// Young-Laplace part, so the small dynamic pressure keeps BF16's relative precision.
 __global__ void k_pack(State5 f, long long npix, int w, Scales sc, bf16* __restrict__ x)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,7 +263,7 @@ __global__ void k_pack(State5 f, long long npix, int w, Scales sc, bf16* __restr
     o[3] = (bf16)((f.v[3][p] - (sc.t_a + sc.t_b * y)) / sc.dT);
     o[4] = (bf16)sc.c4;
     o[5] = (bf16)sc.c5;
-    o[6] = (bf16)(f.v[4][p] / sc.P);
+    o[6] = (bf16)((f.v[4][p] - sc.P * 0.5f * (1.f - f.v[0][p])) / sc.P);
     o[7] = (bf16)0.f;
 }
 
@@ -335,11 +336,11 @@ __global__ void k_frame_final(const double* __restrict__ part, int groups, doubl
 // ---- launchers ----
 
 hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const void* res, const bf16* mask,
-                void* out, int out_f32, int relu_in, int N, int H, int W, hipStream_t s)
+                void* out, int out_f32, int relu_in, int dil, int N, int H, int W, hipStream_t s)
 {
     const long long segs = (long long)N * H * (W / 32);
     hipLaunchKernelGGL(k_conv, dim3((unsigned)((segs + 3) / 4)), dim3(256), 0, s, in, cin, w, bias, res, mask, out,
-                       out_f32, relu_in, N, H, W);
+                       out_f32, relu_in, dil, N, H, W);
     return hipGetLastError();
 }
 
@@ -349,11 +350,11 @@ hipError_t adjoint_weights(const bf16* w, int cin, bf16* wt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int N, int H, int W, float* part, int groups,
-                 float* out, hipStream_t s)
+hipError_t wgrad(const bf16* dy, const bf16* in, int cin, int relu_in, int dil, int N, int H, int W, float* part,
+                 int groups, float* out, hipStream_t s)
 {
     const int ntiles_n = (9 * cin + 31) / 32;
-    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(256), 0, s, dy, in, cin, relu_in, N, H, W, part, ntiles_n);
+    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(256), 0, s, dy, in, cin, relu_in, dil, N, H, W, part, ntiles_n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long width = 32LL * 9 * cin;

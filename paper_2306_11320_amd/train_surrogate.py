@@ -43,17 +43,17 @@ def main(argv=None) -> dict:
     ap.add_argument("--n-train", type=int, default=64)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--K", type=int, default=100)
-    ap.add_argument("--t0", type=int, default=4000)
-    ap.add_argument("--t1", type=int, default=20000)
+    ap.add_argument("--t0", type=int, default=20000)
+    ap.add_argument("--t1", type=int, default=45000)
     ap.add_argument("--stride", type=int, default=500)
-    ap.add_argument("--iters", type=int, default=6000)
+    ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--crop", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--n-eval", type=int, default=8)
     ap.add_argument("--eval-seed", type=int, default=55)
-    ap.add_argument("--warm", type=int, default=10000)
-    ap.add_argument("--blocks", type=int, default=50)
+    ap.add_argument("--warm", type=int, default=30000)
+    ap.add_argument("--blocks", type=int, default=30)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--tol-check", type=float, default=0.01)
     a = ap.parse_args(argv)

@@ -47,26 +47,27 @@ def stream():
 
 @pytest.mark.parametrize("cin", [8, 32])
 @pytest.mark.parametrize("relu_in", [False, True])
-def test_conv_forward(cin, relu_in, stream):
-    rng = np.random.default_rng(cin + relu_in)
+@pytest.mark.parametrize("dil", [1, 3])
+def test_conv_forward(cin, relu_in, dil, stream):
+    rng = np.random.default_rng(cin + relu_in + 10 * dil)
     N, H, W = 2, 5, 64
-    announce("conv_forward", cin, relu_in)
+    announce("conv_forward", cin, relu_in, dil)
     x = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
     w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
     b = rng.standard_normal(32).astype(np.float32)
     res = rng.standard_normal((N, H, W, 32)).astype(np.float32)
     out = torch.empty((N, H, W, 32), device="cuda")
-    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), t_f32(res), None, out, relu_in, stream)
+    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), t_f32(res), None, out, relu_in, stream, dil)
     stream.synchronize()
     a = cr.relu(x) if relu_in else x
-    ref = cr.conv(a, w, b) + res
+    ref = cr.conv(a, w, b, dil) + res
     assert relmax(host(out), ref) <= 2e-5
     # BF16 output with a mask
     mask = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
     outb = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
-    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), None, t_bf16(mask), outb, relu_in, stream)
+    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), None, t_bf16(mask), outb, relu_in, stream, dil)
     stream.synchronize()
-    refb = cr.bf16_round(cr.conv(a, w, b) * (mask > 0))
+    refb = cr.bf16_round(cr.conv(a, w, b, dil) * (mask > 0))
     got = host(outb)
     assert np.all(np.abs(got - refb) <= 2 ** -7 * np.abs(refb) + 1e-6)
 
@@ -75,15 +76,15 @@ def test_adjoint_input_gradient(stream):
     rng = np.random.default_rng(7)
     N, H, W = 1, 6, 32
     announce("adjoint")
-    for cin in (8, 32):
+    for cin, dil in ((8, 1), (32, 1), (32, 2), (8, 5)):
         w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
         g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
         wt = torch.empty((32, 9, 32), dtype=torch.bfloat16, device="cuda")
         sur.sur_adjoint_weights(t_bf16(w), cin, wt, stream)
         out = torch.empty((N, H, W, 32), device="cuda")
-        sur.sur_conv3x3(t_bf16(g), 32, wt, None, None, None, out, False, stream)
+        sur.sur_conv3x3(t_bf16(g), 32, wt, None, None, None, out, False, stream, dil)
         stream.synchronize()
-        ref = cr.conv_input_grad(g, w)
+        ref = cr.conv_input_grad(g, w, dil)
         got = host(out)[..., :cin]
         assert relmax(got, ref) <= 2e-5
         if cin < 32:
@@ -91,19 +92,20 @@ def test_adjoint_input_gradient(stream):
 
 
 @pytest.mark.parametrize("cin", [8, 32])
-def test_weight_and_bias_gradient(cin, stream):
-    rng = np.random.default_rng(11 + cin)
+@pytest.mark.parametrize("dil", [1, 4])
+def test_weight_and_bias_gradient(cin, dil, stream):
+    rng = np.random.default_rng(11 + cin + dil)
     N, H, W = 2, 7, 96
-    announce("wgrad", cin)
+    announce("wgrad", cin, dil)
     a = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
     g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
     for relu_in in (False, True):
         groups = 13
         part = torch.empty(groups * 32 * 9 * cin, device="cuda")
         out = torch.empty((32, 9, cin), device="cuda")
-        sur.sur_weight_grad(t_bf16(g), t_bf16(a), cin, relu_in, part, groups, out, stream)
+        sur.sur_weight_grad(t_bf16(g), t_bf16(a), cin, relu_in, part, groups, out, stream, dil)
         stream.synchronize()
-        ref = cr.conv_weight_grad(g, cr.relu(a) if relu_in else a)
+        ref = cr.conv_weight_grad(g, cr.relu(a) if relu_in else a, dil)
         assert relmax(host(out), ref) <= 2e-5
     bpart = torch.empty(5 * 32, device="cuda")
     bout = torch.empty(32, device="cuda")
@@ -145,13 +147,13 @@ def test_network_gradients_vs_reference():
     announce("network_gradients")
     net = sur.Surrogate(seed=3)
     rng = np.random.default_rng(5)
-    N, H, W = 2, 6, 64
+    N, H, W = 2, 40, 64
     x = np.zeros((N, H, W, 8))
     x[..., :6] = rng.standard_normal((N, H, W, 6))
     x = cr.bf16_round(x)
     target = rng.standard_normal((N, H, W, 4)).astype(np.float32)
     loss, gW, gb, delta = net.gradients(t_bf16(x), t_f32(target))
-    ref = cr.NetRef([w.cpu().numpy() for w in net.W], [b.cpu().numpy() for b in net.b])
+    ref = cr.NetRef([w.cpu().numpy() for w in net.W], [b.cpu().numpy() for b in net.b], net.dil)
     rloss, rgW, rgb, rdelta = ref.loss_and_grads(x, target.astype(np.float64), 1.0)
     assert abs(loss - rloss) <= 1e-3 * rloss
     assert relmax(host(delta)[..., :4], rdelta[..., :4]) <= 2e-2
@@ -220,9 +222,9 @@ def test_pack_target_and_advance(stream):
     want[..., 3] = (H["T"] - (sc.t_a + sc.t_b * y)) / sc.dT
     want[..., 4] = sc.c4
     want[..., 5] = sc.c5
-    want[..., 6] = H["p"] / sc.P
+    want[..., 6] = (H["p"] - sc.P * 0.5 * (1.0 - H["phi"])) / sc.P
     got = host(x)
-    assert np.all(np.abs(got - cr.bf16_round(want)) <= 2 ** -8 * np.abs(want) + 1e-30)
+    assert np.all(np.abs(got - cr.bf16_round(want)) <= 2 ** -8 * np.abs(want) + 1e-6)
     inc = np.array([sc.inc[c] for c in range(5)])
     tt = host(t)
     for c, k in enumerate(sur.FIELDS):
@@ -263,10 +265,12 @@ def test_light_volume_and_judge(stream):
         assert np.isclose(o[2 * c + 1], np.sum((B[k] - rest[k]) ** 2), rtol=1e-12)
 
 
-def test_hybrid_judging_every_block_is_the_lattice_update():
-    """With the judge on every block the hybrid's state is the lattice
-    update's own (bitwise); with a huge tolerance an untrained network runs
-    undisturbed; with a tiny one every judged block falls back."""
+def test_hybrid_bookkeeping():
+    """With a zero tolerance every judged block falls back and the lattice
+    update carries on from its own result: judging every block is then the
+    plain lattice update, bitwise.  With a huge tolerance an untrained network
+    runs undisturbed between judged blocks, and with a tiny one the judged
+    blocks hand the following blocks to the lattice update."""
     from paper_2306_11320_amd import lbm, workloads as wl
     announce("hybrid_bookkeeping")
     cfg, f0 = wl.sweep_instance(64, 256, 12.0, 3.0, 1.5, laplace_p=True)
@@ -275,16 +279,16 @@ def test_hybrid_judging_every_block_is_the_lattice_update():
     fr = ref.fields(0, out="f32", to_host=False)
     lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
     net = sur.Surrogate(seed=2, stream=lat.stream)
-    h = sur.Hybrid(net, lat, cfg, K=100, check_every=1, tol_check=1e9, tol_vol=1e9)
+    h = sur.Hybrid(net, lat, cfg, K=100, check_every=1, tol_check=0.0, fallback_blocks=0)
     st = h.run(3)
-    assert st["lbm_blocks"] == 3 and st["net_blocks"] == 0 and st["judged"] == 3
+    assert st["lbm_blocks"] == 3 and st["net_blocks"] == 0 and st["judged"] == 3 and st["fallbacks"] == 3
     for k in sur.FIELDS:
         assert torch.equal(h.s[k], fr[k]), k
     lat2 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
     net.stream = lat2.stream
     h2 = sur.Hybrid(net, lat2, cfg, K=100, check_every=4, tol_check=1e9, tol_vol=1e9)
     st2 = h2.run(8)
-    assert (st2["net_blocks"], st2["lbm_blocks"], st2["fallbacks"]) == (6, 2, 0)
+    assert (st2["net_blocks"], st2["lbm_blocks"], st2["fallbacks"], st2["judged"]) == (6, 2, 0, 2)
     lat3 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
     net.stream = lat3.stream
     h3 = sur.Hybrid(net, lat3, cfg, K=100, check_every=4, tol_check=0.0, fallback_blocks=2)
@@ -293,3 +297,30 @@ def test_hybrid_judging_every_block_is_the_lattice_update():
     assert (st3["net_blocks"], st3["lbm_blocks"], st3["fallbacks"]) == (6, 4, 2)
     for L in (ref, lat, lat2, lat3):
         L.close()
+
+
+def test_trained_network_gain():
+    """The committed trained network against the plain FP32 lattice update on
+    two fresh droplet lattices (sweep parameters, seed 55), 10 blocks of 100
+    steps after 30000 steps of warm-up: the hybrid is at least twice as fast
+    and needs no fallback; phi and T stay within 1 % and at least 4 times
+    closer to the lattice update than the state they started from
+    (persistence); the velocity, whose per-block change is mostly the
+    lattice's weakly damped sound waves, stays within 1.2 % and closer than
+    persistence."""
+    import os
+    from paper_2306_11320_amd.train_surrogate import sweep_items
+    announce("trained_network_gain")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = sur.Surrogate.load(os.path.join(root, "paper_2306_11320_amd", "weights", "surrogate_k100.npz"))
+    res = sur.evaluate(net, sweep_items(2, 55, 256, 1024), warm=30000, blocks=10, chunk=10, log=None)
+    for r in res:
+        eh, ep = r["err_hybrid"][-1], r["err_persistence"][-1]
+        speedup = sum(r["t_ref_ms"]) / sum(r["t_hybrid_ms"])
+        print(f"speedup {speedup:.2f} hybrid {eh} persistence {ep}", flush=True)
+        assert speedup >= 2.0
+        assert r["fallbacks"] == 0
+        for k in ("phi", "T"):
+            assert eh[k] <= 0.01 and eh[k] <= 0.25 * ep[k], k
+        for k in ("ux", "uy"):
+            assert eh[k] <= 0.012 and eh[k] < ep[k], k

@@ -34,7 +34,28 @@ def test_conv_matches_scipy_correlate():
             assert np.allclose(out[n, :, :, co], acc, atol=1e-12)
 
 
-def test_conv_gradients_by_linearity():
+@pytest.mark.parametrize("dil", [2, 3])
+def test_dilated_conv_matches_scipy_correlate(dil):
+    """A dilation d is the cross-correlation with the 3x3 kernel spread onto a
+    (2d+1) x (2d+1) grid of zeros, on the frame padded by d rows of zeros and
+    wrapped by d columns."""
+    rng = np.random.default_rng(4 + dil)
+    a = rng.standard_normal((1, 6, 8, 2))
+    w = rng.standard_normal((3, 9, 2))
+    out = cr.conv(a, w, dil=dil)
+    for co in range(3):
+        acc = np.zeros((6, 8))
+        for ci in range(2):
+            fr = np.pad(a[0, :, :, ci], ((dil, dil), (0, 0)))
+            fr = np.concatenate([fr[:, -dil:], fr, fr[:, :dil]], axis=1)
+            k = np.zeros((2 * dil + 1, 2 * dil + 1))
+            k[::dil, ::dil] = w[co, :, ci].reshape(3, 3)
+            acc += signal.correlate2d(fr, k, mode="valid")
+        assert np.allclose(out[0, :, :, co], acc, atol=1e-12)
+
+
+@pytest.mark.parametrize("dil", [1, 2])
+def test_conv_gradients_by_linearity(dil):
     """The input and weight gradients are exact for the bilinear form
     <conv(a, w), g>: checked by directional derivatives (exact for a linear map)."""
     rng = np.random.default_rng(2)
@@ -43,9 +64,9 @@ def test_conv_gradients_by_linearity():
     g = rng.standard_normal((1, 4, 6, 5))
     da = rng.standard_normal(a.shape)
     dw = rng.standard_normal(w.shape)
-    f = lambda aa, ww: np.sum(cr.conv(aa, ww) * g)  # noqa: E731
-    assert np.isclose(f(a + da, w) - f(a, w), np.sum(cr.conv_input_grad(g, w) * da), rtol=1e-11)
-    assert np.isclose(f(a, w + dw) - f(a, w), np.sum(cr.conv_weight_grad(g, a) * dw), rtol=1e-11)
+    f = lambda aa, ww: np.sum(cr.conv(aa, ww, dil=dil) * g)  # noqa: E731
+    assert np.isclose(f(a + da, w) - f(a, w), np.sum(cr.conv_input_grad(g, w, dil) * da), rtol=1e-11)
+    assert np.isclose(f(a, w + dw) - f(a, w), np.sum(cr.conv_weight_grad(g, a, dil) * dw), rtol=1e-11)
 
 
 def test_net_gradients_finite_difference():
@@ -64,7 +85,8 @@ def test_net_gradients_finite_difference():
     saved = cr.bf16_round, cr.fp32_round
     cr.bf16_round = cr.fp32_round = lambda v: np.asarray(v, np.float64)  # exact storage for the check
     try:
-        net = cr.NetRef(W, b)
+        dil = (1, 2, 1, 3, 1, 2)
+        net = cr.NetRef(W, b, dil)
         loss, gW, gb, _ = net.loss_and_grads(x, target, 1.0)
         for layer, (co, t, ci) in ((0, (3, 4, 2)), (2, (7, 0, 11)), (5, (1, 8, 30))):
             e = 1e-6
@@ -72,14 +94,15 @@ def test_net_gradients_finite_difference():
             Wp[layer][co, t, ci] += e
             Wm = [w.copy() for w in W]
             Wm[layer][co, t, ci] -= e
-            lp = cr.NetRef(Wp, b).loss_and_grads(x, target, 1.0)[0]
-            lm = cr.NetRef(Wm, b).loss_and_grads(x, target, 1.0)[0]
+            lp = cr.NetRef(Wp, b, dil).loss_and_grads(x, target, 1.0)[0]
+            lm = cr.NetRef(Wm, b, dil).loss_and_grads(x, target, 1.0)[0]
             assert np.isclose((lp - lm) / (2 * e), gW[layer][co, t, ci], rtol=1e-5, atol=1e-9)
         bp = [v.copy() for v in b]
         bp[3][5] += 1e-6
         bm = [v.copy() for v in b]
         bm[3][5] -= 1e-6
-        d = (cr.NetRef(W, bp).loss_and_grads(x, target, 1.0)[0] - cr.NetRef(W, bm).loss_and_grads(x, target, 1.0)[0]) / 2e-6
+        d = (cr.NetRef(W, bp, dil).loss_and_grads(x, target, 1.0)[0]
+             - cr.NetRef(W, bm, dil).loss_and_grads(x, target, 1.0)[0]) / 2e-6
         assert np.isclose(d, gb[3][5], rtol=1e-5, atol=1e-9)
     finally:
         cr.bf16_round, cr.fp32_round = saved
