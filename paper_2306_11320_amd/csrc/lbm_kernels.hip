@@ -23,6 +23,14 @@
 
 namespace lbm {
 
+// Global-memory views of the lattice pointers: accesses through them compile
+// to global_* instructions; generic pointers give flat_* ones, which also
+// count against the LDS wait counter and so stall behind the patch traffic.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
 enum { BC_PERIODIC = 0, BC_WALL_T = 1, BC_WALL_ADIABATIC = 2, BC_INLET = 3, BC_OUTLET = 4 };
 
 // D2Q9 (Sec. 4 preamble): c_0 = (0,0); c_1..4 = (1,0),(0,1),(-1,0),(0,-1);
@@ -116,7 +124,7 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 template <typename real, int TX, int TY, bool EDGE>
-__device__ inline void fill_entry(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int q,
+__device__ inline void fill_entry(const Inst<real>& I, gptr<const real> __restrict__ A, Patch<real, TX, TY>& S, int q,
                                   int gx, int gy)
 {
     int sx, sy;
@@ -150,7 +158,7 @@ __device__ inline void fill_entry(const Inst<real>& I, const real* __restrict__ 
 // Loads the work-item's own node and fills the patch.  Returns whether the
 // work-item's node lies in the lattice.
 template <typename real, int TX, int TY, bool EDGE>
-__device__ inline bool load_patch(const Inst<real>& I, const real* __restrict__ A, Patch<real, TX, TY>& S, int x0,
+__device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restrict__ A, Patch<real, TX, TY>& S, int x0,
                                   int y0, real (&f)[9], real (&g)[9], real (&h)[9])
 {
     using PT = Patch<real, TX, TY>;
@@ -296,8 +304,9 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
 {
     using PT = Patch<real, TX, TY>;
     constexpr int PX = PT::PX;
-    const real* __restrict__ A = I.pop[src];
-    real* __restrict__ B = I.pop[src ^ 1];
+    const gptr<const real> __restrict__ A = to_global<const real>(I.pop[src]);
+    const gptr<real> __restrict__ B = to_global(I.pop[src ^ 1]);
+    const gptr<real> __restrict__ J = to_global(I.jprev);
     real f[9], g[9], h[9];
     const bool inside = load_patch<real, TX, TY, EDGE>(I, A, S, x0, y0, f, g, h);
     if (!inside) return;
@@ -306,7 +315,7 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const int c = (tid / TX + 1) * PX + (tid % TX + 1);
     const long long P = I.plane;
     const long long own = (long long)gj * I.pitch + gi;
-    const real jpx = I.jprev[own], jpy = I.jprev[P + own];
+    const real jpx = J[own], jpy = J[P + own];
 
     const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
     const real phi = m.phi, ux = m.ux, uy = m.uy;
@@ -322,8 +331,8 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     // time derivative of phi u by the first-order Euler scheme; store phi u
     const real jx = phi * ux, jy = phi * uy;
     const real djx = jx - jpx, djy = jy - jpy;
-    I.jprev[own] = jx;
-    I.jprev[P + own] = jy;
+    J[own] = jx;
+    J[P + own] = jy;
 
     // Allen-Cahn source: unit normal from v = sum c_i (f_i - f_i^eq) + dt(phi u)/2, n = -v/|v|
     real nxv = 0, nyv = 0;
@@ -366,65 +375,62 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const real p3 = real(3) * m.p;
     const real theta = m.theta;
 
-    real fs[9], gs[9], hs[9];
+    // Collision (Eq. 14, the NS LBE, Eq. 28) and push streaming, one direction
+    // at a time so that each post-collision value is stored as soon as it
+    // exists.  The thermal update at the destination y = x + c_i is
+    // h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y).
+    // The rest populations come last and take the balance:
+    // f*_0 = f_0 + sum_{i>0} (f_i - f*_i), h*_0 = h_0 + Fhat + sum_{i>0} (h_i - h*_i),
+    // equal to their BGK values in real arithmetic (sum_i f*_i = sum_i f_i,
+    // sum_i h*_i = sum_i h_i + Fhat); this keeps the stored update mass- and
+    // heat-neutral up to one rounding.  Otherwise each node relaxes toward w_i
+    // times its rounded moment, and identical bulk nodes round alike, so FP32
+    // storage drifts linearly in time.
+    real df = 0, dh = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int kk = 1; kk <= 9; ++kk) {
+        const int k = kk % 9;  // directions 1..8, then the rest population
         const real w = wgt<real>(k);
         const real cu = real(cx(k)) * ux + real(cy(k)) * uy;
-        // Eq. 14: f* = f - (f - f^eq)/tau_phi + (1 - 1/(2 tau_phi)) R_i
-        const real feq = w * (m.dphi + real(3) * phi * cu);
-        const real Ri = w * (real(cx(k)) * ax + real(cy(k)) * ay);
-        fs[k] = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
         // NS LBE: g^eq = 3 p (w_i - delta_i0) + rho s_i(u); G_i = w_i [3 c_i.F + 3 (c_i.u)(c_i.grad rho)]
         const real si = w * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
         const real geq = (k == 0 ? p3 * (w - real(1)) : p3 * w) + m.rho * si;
         const real cF = real(cx(k)) * m.Fx + real(cy(k)) * m.Fy;
         const real cg = real(cx(k)) * m.grx + real(cy(k)) * m.gry;
         const real Gi = w * real(3) * (cF + cu * cg);
-        gs[k] = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
-        // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat
-        hs[k] = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
-    }
-    // The rest populations take the balance: f*_0 = f_0 + sum_{i>0} (f_i - f*_i)
-    // equals the BGK value exactly in real arithmetic (sum_i f*_i = sum_i f_i,
-    // sum_i h*_i = sum_i h_i + Fhat), and keeps the stored update mass- and
-    // heat-neutral up to one rounding.  Otherwise each node relaxes toward
-    // w_i times its rounded moment, and identical bulk nodes round alike, so
-    // FP32 storage drifts linearly in time.
-    {
-        real df = 0, dh = 0;
-#pragma unroll
-        for (int k = 1; k < 9; ++k) {
-            df += f[k] - fs[k];
-            dh += h[k] - hs[k];
+        const real gsk = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
+        real fsk, hsk;
+        if (k == 0) {
+            fsk = f[0] + df;
+            hsk = (h[0] + Fhat) + dh;
+        } else {
+            // Eq. 14: f* = f - (f - f^eq)/tau_phi + (1 - 1/(2 tau_phi)) R_i
+            const real feq = w * (m.dphi + real(3) * phi * cu);
+            const real Ri = w * (real(cx(k)) * ax + real(cy(k)) * ay);
+            fsk = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
+            // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat
+            hsk = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
+            df += f[k] - fsk;
+            dh += h[k] - hsk;
         }
-        fs[0] = f[0] + df;
-        hs[0] = (h[0] + Fhat) + dh;
-    }
-
-    // push streaming; thermal update at the destination y = x + c_i:
-    // h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y)
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
         long long di;
         int side;
         if (dest<real, EDGE>(I, gi, gj, k, di, side)) {
             const int cd = c + cy(k) * PX + cx(k);
-            B[(kF + k) * P + di] = fs[k];
-            B[(kG + k) * P + di] = gs[k];
+            B[(kF + k) * P + di] = fsk;
+            B[(kG + k) * P + di] = gsk;
             const real hold = S.h[k][cd];
-            B[(kH + k) * P + di] = hold + (hs[k] - hold) * S.irc[cd];
+            B[(kH + k) * P + di] = hold + (hsk - hold) * S.irc[cd];
         } else if (EDGE) {
             const int kb = opp(k);
             const int bc = I.bc[side];
-            const real w = wgt<real>(k);
             const real s = side < 2 ? real(gj) + real(0.5) * real(cy(k)) : real(gi) + real(0.5) * real(cx(k));
             real fb, gb, hb;
             if (bc == BC_WALL_T || bc == BC_WALL_ADIABATIC) {
                 // halfway bounce-back; anti-bounce-back for a Dirichlet temperature
-                fb = fs[k];
-                gb = gs[k];
-                hb = bc == BC_WALL_T ? -hs[k] + real(2) * w * wall_T(I, side, s) : hs[k];
+                fb = fsk;
+                gb = gsk;
+                hb = bc == BC_WALL_T ? -hsk + real(2) * w * wall_T(I, side, s) : hsk;
             } else if (bc == BC_INLET) {
                 // anti-bounce-back for phi and T, moving-wall bounce-back for u
                 const real H = side < 2 ? real(I.ny) : real(I.nx);
@@ -432,14 +438,13 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
                 const real un = real(6) * I.u_in * sp * (H - sp) / (H * H);
                 const real uix = side == 0 ? un : (side == 1 ? -un : real(0));
                 const real uiy = side == 2 ? un : (side == 3 ? -un : real(0));
-                fb = -fs[k] + real(2) * w * I.phi_in_d;
-                gb = gs[k] - real(6) * w * m.rho * (real(cx(k)) * uix + real(cy(k)) * uiy);
-                hb = -hs[k] + real(2) * w * I.T_in_d;
+                fb = -fsk + real(2) * w * I.phi_in_d;
+                gb = gsk - real(6) * w * m.rho * (real(cx(k)) * uix + real(cy(k)) * uiy);
+                hb = -hsk + real(2) * w * I.T_in_d;
             } else {  // outlet: anti-bounce-back at p = 0 with the node's own u, phi, T
-                const real cu = real(cx(k)) * ux + real(cy(k)) * uy;
-                fb = -fs[k] + real(2) * w * m.dphi;
-                gb = -gs[k] + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * uu);
-                hb = -hs[k] + real(2) * w * theta;
+                fb = -fsk + real(2) * w * m.dphi;
+                gb = -gsk + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * uu);
+                hb = -hsk + real(2) * w * theta;
             }
             B[(kF + kb) * P + own] = fb;
             B[(kG + kb) * P + own] = gb;
@@ -495,8 +500,8 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+                                ? load_patch<real, TX, TY, false>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -504,8 +509,9 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
             const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX>(I, S.phi, S.T, c, g);
             if (jprev_out) {
                 const long long own = (long long)gj * I.pitch + gi;
-                I.jprev[own] = m.phi * m.ux;
-                I.jprev[I.plane + own] = m.phi * m.uy;
+                const gptr<real> J = to_global(I.jprev);
+                J[own] = m.phi * m.ux;
+                J[I.plane + own] = m.phi * m.uy;
             } else {
                 const long long o = (long long)gj * I.nx + gi;
                 const double phi = (double)I.phi0 + (double)m.dphi;
@@ -541,7 +547,7 @@ __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __res
     if (x >= n) return;
     const int i = (int)(x % I.nx), j = (int)(x / I.nx);
     const double phi = staged[x], ux = staged[n + x], uy = staged[2 * n + x], T = staged[3 * n + x];
-    real* __restrict__ A = I.pop[src];
+    const gptr<real> __restrict__ A = to_global(I.pop[src]);
     const long long P = I.plane, idx = (long long)j * I.pitch + i;
     if (!shift) {
         const double p = has_p ? staged[4 * n + x] : 0.0;
@@ -640,8 +646,8 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, I.pop[src], S, tl.x0, tl.y0, f, g, h);
+                                ? load_patch<real, TX, TY, false>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;

@@ -166,3 +166,82 @@ def test_autotune_keeps_results(tmp_path):
     c = lbm.Lattice.batch(items, lbm.FP32_DEV)
     res2 = c.autotune(steps_per_trial=2, cache=cache)
     assert res2["cached"] and res2["tile"] == res["tile"] and c.tile() == res["tile"]
+
+
+# ---- restarts from device fields ---------------------------------------------
+
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+WGT = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def _device(fields, dtype="float64"):
+    import torch
+    return {k: torch.as_tensor(np.ascontiguousarray(v, dtype=dtype)).cuda() for k, v in fields.items()}
+
+
+def test_reinit_equilibrium_with_pressure():
+    """An equilibrium restart at given (phi, u, T, p) writes the equilibria of
+    the three LBEs (Eqs. 9, 17, 33) and the moments give the fields back
+    (uniform phi, no gravity: no force term in the velocity)."""
+    announce("reinit_equilibrium")
+    cfg, f0 = wl.tiny(64, 40, seed=5)
+    cfg["Gx"] = cfg["Gy"] = 0.0
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    rng = np.random.default_rng(8)
+    ny, nx = 40, 64
+    j, i = np.mgrid[0:ny, 0:nx]
+    new = dict(phi=np.ones((ny, nx)),
+               ux=1e-3 * np.sin(2 * np.pi * i / nx) * np.cos(np.pi * j / ny),
+               uy=5e-4 * np.cos(2 * np.pi * i / nx),
+               T=1.0 + 0.1 * rng.standard_normal((ny, nx)),
+               p=1e-4 * np.sin(np.pi * j / ny))
+    lat.reinit_fields(_device(new))
+    st = lat.get_state(0)
+    rho = cfg["rho_h"]      # phi = 1 everywhere
+    cu = CX[:, None, None] * new["ux"] + CY[:, None, None] * new["uy"]
+    uu = new["ux"] ** 2 + new["uy"] ** 2
+    w = WGT[:, None, None]
+    f_eq = w * new["phi"] * (1 + 3 * cu)
+    g_eq = 3 * new["p"] * (w - (np.arange(9) == 0)[:, None, None]) + rho * w * (3 * cu + 4.5 * cu ** 2 - 1.5 * uu)
+    h_eq = w * new["T"]
+    assert np.allclose(st["f"], f_eq, rtol=0, atol=1e-15)
+    assert np.allclose(st["g"], g_eq, rtol=0, atol=1e-17)
+    assert np.allclose(st["h"], h_eq, rtol=0, atol=1e-15)
+    got = lat.fields()
+    for k in ("phi", "T"):
+        assert np.max(np.abs(got[k] - new[k])) <= 1e-14, k
+    for k in ("ux", "uy", "p"):
+        assert np.max(np.abs(got[k] - new[k])) <= 1e-14 * np.max(np.abs(new[k])) + 1e-19, k
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_DEV], ids=["fp64", "fp32dev"])
+def test_reinit_shift_keeps_non_equilibrium(prec):
+    """A shift restart at the lattice's own fields leaves the populations as
+    they are (the equilibria cancel); with T raised by dT everywhere only the
+    thermal populations move, by w_i dT."""
+    announce("reinit_shift", prec)
+    cfg, f0 = wl.tiny(64, 40, seed=6)
+    lat = lbm.Lattice(cfg, f0, prec)
+    lat.step(41)
+    st0 = lat.get_state(0)
+    cur = lat.fields()
+    lat.reinit_fields(_device(cur), shift=True)
+    st1 = lat.get_state(0)
+    tol = 1e-15 if prec == lbm.FP64 else 0.0
+    for k in ("f", "g", "h"):
+        assert np.max(np.abs(st1[k] - st0[k])) <= tol * np.max(np.abs(st0[k])), k
+    jp = st1["jprev"]
+    assert np.allclose(jp[0], cur["phi"] * cur["ux"], rtol=1e-6 if prec else 1e-13, atol=1e-12)
+    assert np.allclose(jp[1], cur["phi"] * cur["uy"], rtol=1e-6 if prec else 1e-13, atol=1e-12)
+    dT = 0.25
+    hot = dict(cur, T=cur["T"] + dT)
+    lat.reinit_fields(_device(hot), shift=True)
+    st2 = lat.get_state(0)
+    for k in ("f", "g"):
+        assert np.max(np.abs(st2[k] - st1[k])) <= tol * np.max(np.abs(st1[k])), k
+    d = st2["h"] - st1["h"]
+    want = WGT[:, None, None] * dT * np.ones_like(d)
+    assert np.allclose(d, want, rtol=0, atol=1e-15 if prec == lbm.FP64 else 2e-7)
+    lat.close()
