@@ -55,7 +55,9 @@ int validate(const lbm_params& p)
 {
     if (p.abi_version != LBM_ABI_VERSION) return fail(LBM_EINVAL, "abi_version %u != %u", p.abi_version, LBM_ABI_VERSION);
     if (p.nx < 3 || p.ny < 3) return fail(LBM_EINVAL, "lattice %ux%u smaller than 3x3", p.nx, p.ny);
-    if ((uint64_t)p.nx * p.ny > (1ull << 31)) return fail(LBM_EINVAL, "lattice too large");
+    // node offsets within a population plane are 32-bit byte offsets in the kernels
+    if ((uint64_t)(p.nx + 31) / 32 * 32 * p.ny >= (1ull << 28))
+        return fail(LBM_EINVAL, "lattice too large (%ux%u): at most 2^28 nodes", p.nx, p.ny);
     if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return fail(LBM_EINVAL, "unknown precision %u", p.precision);
     for (int s = 0; s < 4; ++s)
         if (p.bc[s] > LBM_BC_OUTLET) return fail(LBM_EINVAL, "unknown boundary kind %u on side %d", p.bc[s], s);

@@ -31,6 +31,38 @@ using gptr = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ inline gptr<T> to_global(T* p) { return (gptr<T>)p; }
 
+// Reciprocals: the hardware's (1 ulp) in FP32, correctly rounded in FP64.
+// The FP32 reciprocal square root flushes subnormal inputs, so unit vectors
+// are only formed from squared lengths of at least the smallest normal
+// float (below it the direction is rounding noise and the vector is zero).
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ inline bool has_direction(float n2) { return n2 >= 1.17549435e-38f; }
+__device__ inline bool has_direction(double n2) { return n2 > 0.0; }
+
+// Node offsets within a population plane are 32-bit (the host checks that a
+// plane holds fewer than 2^29 nodes); the plane base is uniform, so loads and
+// stores take a scalar base and a 32-bit vector offset.
+// Base of population plane q: the same in every lane, and made a scalar
+// value so that the compiler keeps it in scalar registers.
+template <typename T>
+__device__ inline gptr<T> plane_of(gptr<T> base, int q, long long plane)
+{
+    const unsigned long long v = (unsigned long long)(base + (size_t)q * (size_t)plane);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+// Element at a 32-bit byte offset from a (uniform) base.
+template <typename T>
+__device__ inline T ld(gptr<const T> base, unsigned off) { return *(gptr<const T>)((gptr<const char>)base + off); }
+template <typename T>
+__device__ inline T ld(gptr<T> base, unsigned off) { return *(gptr<const T>)((gptr<const char>)base + off); }
+template <typename T>
+__device__ inline void st(gptr<T> base, unsigned off, T v) { *(gptr<T>)((gptr<char>)base + off) = v; }
+
 enum { BC_PERIODIC = 0, BC_WALL_T = 1, BC_WALL_ADIABATIC = 2, BC_INLET = 3, BC_OUTLET = 4 };
 
 // D2Q9 (Sec. 4 preamble): c_0 = (0,0); c_1..4 = (1,0),(0,1),(-1,0),(0,-1);
@@ -137,19 +169,18 @@ __device__ inline void fill_entry(const Inst<real>& I, gptr<const real> __restri
         sx = wrap1(gx, I.nx);
         sy = wrap1(gy, I.ny);
     }
-    const long long P = I.plane;
-    const long long idx = (long long)sy * I.pitch + sx;
+    const unsigned idx = (unsigned)(sy * I.pitch + sx);
     real sf = 0, sh = 0, hk[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        sf += A[(kF + k) * P + idx];
-        hk[k] = A[(kH + k) * P + idx];
+        sf += ld(plane_of(A, kF + k, I.plane), idx * (unsigned)sizeof(real));
+        hk[k] = ld(plane_of(A, kH + k, I.plane), idx * (unsigned)sizeof(real));
         sh += hk[k];
     }
     const real dphi = EDGE ? aphi + sphi * sf : sf;
     S.phi[q] = dphi;
     S.T[q] = EDGE ? aT + sT * sh : sh;
-    S.irc[q] = real(1) / (I.rcp_a + I.rcp_b * (I.phi0 + dphi));
+    S.irc[q] = recip(I.rcp_a + I.rcp_b * (I.phi0 + dphi));
 #pragma unroll
     for (int k = 0; k < 9; ++k) S.h[k][q] = rn ? hk[k] : real(0);
     (void)aphi; (void)sphi; (void)aT; (void)sT;
@@ -168,14 +199,13 @@ __device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restri
     const bool inside = gi < I.nx && gj < I.ny;
     const int c = (ly + 1) * PT::PX + (lx + 1);
     if (inside) {
-        const long long P = I.plane;
-        const long long idx = (long long)gj * I.pitch + gi;
+        const unsigned idx = (unsigned)(gj * I.pitch + gi);
         real sf = 0, sh = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = A[(kF + k) * P + idx];
-            h[k] = A[(kH + k) * P + idx];
-            g[k] = A[(kG + k) * P + idx];
+            f[k] = ld(plane_of(A, kF + k, I.plane), idx * (unsigned)sizeof(real));
+            h[k] = ld(plane_of(A, kH + k, I.plane), idx * (unsigned)sizeof(real));
+            g[k] = ld(plane_of(A, kG + k, I.plane), idx * (unsigned)sizeof(real));
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -184,7 +214,7 @@ __device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restri
         }
         S.phi[c] = sf;
         S.T[c] = sh;
-        S.irc[c] = real(1) / (I.rcp_a + I.rcp_b * (I.phi0 + sf));
+        S.irc[c] = recip(I.rcp_a + I.rcp_b * (I.phi0 + sf));
 #pragma unroll
         for (int k = 0; k < 9; ++k) S.h[k][c] = h[k];
     } else {
@@ -237,7 +267,7 @@ __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __res
     m.theta = sT[c];
     const real phi = m.phi;
     m.rho = I.rho_a + I.rho_b * phi;
-    m.irho = real(1) / m.rho;
+    m.irho = recip(m.rho);
     m.grx = I.rho_b * m.gpx;
     m.gry = I.rho_b * m.gpy;
     // chemical potential phi^3 - phi - W^2 lap phi, written so that phi - 1 is exact near phi0 = 1
@@ -270,10 +300,10 @@ __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __res
 // destination index if it stays in the lattice (after periodic wrap);
 // otherwise returns false and the side whose rule applies.
 template <typename real, bool EDGE>
-__device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, long long& idx, int& side)
+__device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, unsigned& idx, int& side)
 {
     if (!EDGE) {
-        idx = (long long)wrap1(gj + cy(k), I.ny) * I.pitch + wrap1(gi + cx(k), I.nx);
+        idx = (unsigned)(wrap1(gj + cy(k), I.ny) * I.pitch + wrap1(gi + cx(k), I.nx));
         side = 0;
         return true;
     }
@@ -285,7 +315,7 @@ __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, long lon
     if (tj < 0) { sys = 2; if (I.bc[2] == BC_PERIODIC) tj += I.ny; else oy = true; }
     else if (tj >= I.ny) { sys = 3; if (I.bc[3] == BC_PERIODIC) tj -= I.ny; else oy = true; }
     if (!ox && !oy) {
-        idx = (long long)tj * I.pitch + ti;
+        idx = (unsigned)(tj * I.pitch + ti);
         return true;
     }
     if (ox && oy) {
@@ -314,8 +344,18 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const int gi = x0 + tid % TX, gj = y0 + tid / TX;
     const int c = (tid / TX + 1) * PX + (tid % TX + 1);
     const long long P = I.plane;
-    const long long own = (long long)gj * I.pitch + gi;
-    const real jpx = J[own], jpy = J[P + own];
+    const unsigned own = (unsigned)(gj * I.pitch + gi);
+    const real jpx = ld(plane_of(J, 0, P), own * (unsigned)sizeof(real)), jpy = ld(plane_of(J, 1, P), own * (unsigned)sizeof(real));
+    // destination rows and columns of the interior path (periodic wrap only)
+    unsigned drow[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
+    if (!EDGE) {
+        drow[0] = (unsigned)(wrap1(gj - 1, I.ny) * I.pitch);
+        drow[1] = (unsigned)(gj * I.pitch);
+        drow[2] = (unsigned)(wrap1(gj + 1, I.ny) * I.pitch);
+        dcol[0] = (unsigned)wrap1(gi - 1, I.nx);
+        dcol[1] = (unsigned)gi;
+        dcol[2] = (unsigned)wrap1(gi + 1, I.nx);
+    }
 
     const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
     const real phi = m.phi, ux = m.ux, uy = m.uy;
@@ -323,16 +363,16 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const real lam = I.lam_a + I.lam_b * phi;
     const real rcp = I.rcp_a + I.rcp_b * phi;
     // mu = rho c_s^2 (tau_g - 1/2), lambda = c_s^2 (tau_h - 1/2)
-    const real inv_tau_g = m.rho / (real(0.5) * m.rho + real(3) * mu);
+    const real inv_tau_g = m.rho * recip(real(0.5) * m.rho + real(3) * mu);
     const real fac_g = real(1) - real(0.5) * inv_tau_g;
     const real tau_h = real(0.5) + real(3) * lam;
-    const real inv_tau_h = real(1) / tau_h;
+    const real inv_tau_h = recip(tau_h);
 
     // time derivative of phi u by the first-order Euler scheme; store phi u
     const real jx = phi * ux, jy = phi * uy;
     const real djx = jx - jpx, djy = jy - jpy;
-    J[own] = jx;
-    J[P + own] = jy;
+    st(plane_of(J, 0, P), own * (unsigned)sizeof(real), jx);
+    st(plane_of(J, 1, P), own * (unsigned)sizeof(real), (real)(jy));
 
     // Allen-Cahn source: unit normal from v = sum c_i (f_i - f_i^eq) + dt(phi u)/2, n = -v/|v|
     real nxv = 0, nyv = 0;
@@ -340,15 +380,15 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
         const real vx = ((f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7])) - jx + real(0.5) * djx;
         const real vy = ((f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8])) - jy + real(0.5) * djy;
         const real vn2 = vx * vx + vy * vy;
-        if (vn2 > real(0)) {
-            const real iv = real(1) / sqrt(vn2);
+        if (has_direction(vn2)) {
+            const real iv = rsq(vn2);
             nxv = -vx * iv;
             nyv = -vy * iv;
         }
     } else {
         const real gn2 = m.gpx * m.gpx + m.gpy * m.gpy;
-        if (gn2 > real(0)) {
-            const real ig = real(1) / sqrt(gn2);
+        if (has_direction(gn2)) {
+            const real ig = rsq(gn2);
             nxv = m.gpx * ig;
             nyv = m.gpy * ig;
         }
@@ -413,14 +453,17 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
             df += f[k] - fsk;
             dh += h[k] - hsk;
         }
-        long long di;
-        int side;
-        if (dest<real, EDGE>(I, gi, gj, k, di, side)) {
+        unsigned di = 0;
+        int side = 0;
+        bool in_lattice = true;
+        if (EDGE) in_lattice = dest<real, EDGE>(I, gi, gj, k, di, side);
+        else di = drow[cy(k) + 1] + dcol[cx(k) + 1];
+        if (in_lattice) {
             const int cd = c + cy(k) * PX + cx(k);
-            B[(kF + k) * P + di] = fsk;
-            B[(kG + k) * P + di] = gsk;
+            st(plane_of(B, kF + k, P), di * (unsigned)sizeof(real), (real)(fsk));
+            st(plane_of(B, kG + k, P), di * (unsigned)sizeof(real), (real)(gsk));
             const real hold = S.h[k][cd];
-            B[(kH + k) * P + di] = hold + (hsk - hold) * S.irc[cd];
+            st(plane_of(B, kH + k, P), di * (unsigned)sizeof(real), (real)(hold + (hsk - hold) * S.irc[cd]));
         } else if (EDGE) {
             const int kb = opp(k);
             const int bc = I.bc[side];
@@ -446,10 +489,10 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
                 gb = -gsk + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * uu);
                 hb = -hsk + real(2) * w * theta;
             }
-            B[(kF + kb) * P + own] = fb;
-            B[(kG + kb) * P + own] = gb;
+            st(plane_of(B, kF + kb, P), own * (unsigned)sizeof(real), (real)(fb));
+            st(plane_of(B, kG + kb, P), own * (unsigned)sizeof(real), (real)(gb));
             const real hold = S.h[kb][c];
-            B[(kH + kb) * P + own] = hold + (hb - hold) * S.irc[c];
+            st(plane_of(B, kH + kb, P), own * (unsigned)sizeof(real), (real)(hold + (hb - hold) * S.irc[c]));
         }
     }
 }
