@@ -38,54 +38,75 @@ __device__ inline bf16x8 relu8(bf16x8 v)
 __device__ inline float to_f(bf16 v) { return (float)v; }
 
 // out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + d dy, x + d dx, ci) W[co][tap][ci] )
-// with dilation d; A = relu(in) if relu_in.  Epilogue: + bias[co]; then, if mask, zero where
-// mask <= 0; then, if res, + res.  The output is FP32 or BF16.
-__global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, int cin, const bf16* __restrict__ w,
+// with dilation d; A = relu(in) if RELU.  Epilogue: + bias[co] (if bias);
+// then, if MASK, zero where mask <= 0; then, if RES, + res.  The output is
+// FP32 if OUTF32, else BF16.  Per 32-pixel segment all K / 16 input operands
+// are loaded before the first matrix-core op (rows outside the frame load a
+// clamped row and are zeroed), so the loads of a wave are in flight together.
+template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
+__global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                               const float* __restrict__ bias, const void* __restrict__ res,
-                                              const bf16* __restrict__ mask, void* __restrict__ out, int out_f32,
-                                              int relu_in, int dil, int N, int H, int W)
+                                              const bf16* __restrict__ mask, void* __restrict__ out, int dil, int N,
+                                              int H, int W)
 {
+    constexpr int K = 9 * CIN, NKB = (K + 15) / 16;
     const int lane = threadIdx.x % 64;
-    const long long seg = (long long)blockIdx.x * 4 + threadIdx.x / 64;  // 32-pixel segment
     const int segs_per_row = W / 32;
-    if (seg >= (long long)N * H * segs_per_row) return;
-    const int x0 = (int)(seg % segs_per_row) * 32;
-    const long long ny = seg / segs_per_row;
-    const int y = (int)(ny % H), n = (int)(ny / H);
+    const long long nseg = (long long)N * H * segs_per_row;
+    const long long wave0 = (long long)blockIdx.x * 4 + threadIdx.x / 64;
+    const long long nwaves = (long long)gridDim.x * 4;
+    if (wave0 >= nseg) return;
     const int m = lane % 32, kh = lane / 32;
-    const int K = 9 * cin;
-    f32x16 acc = {};
-    for (int kb = 0; kb < K; kb += 16) {
-        const int kk = kb + 8 * kh;
-        bf16x8 a = {}, b = {};
-        if (kk < K) {
-            const int tap = kk / cin, ci = kk % cin;
-            const int dy = (tap / 3 - 1) * dil, dx = (tap % 3 - 1) * dil;
-            const int yy = y + dy;
-            int xx = x0 + m + dx;  // |dx| <= W, so one wrap suffices
-            xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
-            if (yy >= 0 && yy < H) {
-                a = load8(in + (((long long)n * H + yy) * W + xx) * cin + ci);
-                if (relu_in) a = relu8(a);
-            }
-            b = load8(w + ((long long)m * 9 + tap) * cin + ci);  // column co = lane % 32
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    // the weight operands of the whole K loop stay in registers while the
+    // wave walks its 32-pixel segments
+    bf16x8 b[NKB];
+#pragma unroll
+    for (int q = 0; q < NKB; ++q) {
+        const int kk = q * 16 + 8 * kh;
+        const bool kv = kk < K;
+        const int kc = kv ? kk : 0;
+        b[q] = load8(w + ((long long)m * 9 + kc / CIN) * CIN + kc % CIN);  // column co = lane % 32
+        if (!kv) b[q] = bf16x8{};
     }
     const int co = lane % 32;
     const float bv = bias ? bias[co] : 0.f;
+    for (long long seg = wave0; seg < nseg; seg += nwaves) {
+        const int x0 = (int)(seg % segs_per_row) * 32;
+        const long long ny = seg / segs_per_row;
+        const int y = (int)(ny % H), n = (int)(ny / H);
+        bf16x8 a[NKB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int px = x0 + 8 * (i / 4) + 4 * kh + (i % 4);
-        const long long idx = (((long long)n * H + y) * W + px) * 32 + co;
-        float v = acc[i] + bv;
-        if (mask && !(to_f(mask[idx]) > 0.f)) v = 0.f;
-        if (out_f32) {
-            if (res) v += static_cast<const float*>(res)[idx];
-            static_cast<float*>(out)[idx] = v;
-        } else {
-            if (res) v += to_f(static_cast<const bf16*>(res)[idx]);
-            static_cast<bf16*>(out)[idx] = (bf16)v;
+        for (int q = 0; q < NKB; ++q) {
+            const int kk = q * 16 + 8 * kh;
+            const bool kv = kk < K;
+            const int kc = kv ? kk : 0;
+            const int tap = kc / CIN, ci = kc % CIN;
+            const int yy = y + (tap / 3 - 1) * dil;
+            int xx = x0 + m + (tap % 3 - 1) * dil;  // |offset| <= W, so one wrap suffices
+            xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+            const bool ok = kv && yy >= 0 && yy < H;
+            const int yc = ok ? yy : y;
+            a[q] = load8(in + (((long long)n * H + yc) * W + xx) * CIN + ci);
+            if (!ok) a[q] = bf16x8{};
+        }
+        f32x16 acc = {};
+#pragma unroll
+        for (int q = 0; q < NKB; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], b[q], acc, 0, 0, 0);
+        const long long row = ((long long)n * H + y) * W;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int px = x0 + 8 * (i / 4) + 4 * kh + (i % 4);
+            const long long idx = (row + px) * 32 + co;
+            float v = acc[i] + bv;
+            if (MASK) v = to_f(mask[idx]) > 0.f ? v : 0.f;
+            if (OUTF32) {
+                if (RES) v += static_cast<const float*>(res)[idx];
+                static_cast<float*>(out)[idx] = v;
+            } else {
+                if (RES) v += to_f(static_cast<const bf16*>(res)[idx]);
+                static_cast<bf16*>(out)[idx] = (bf16)v;
+            }
         }
     }
 }
@@ -323,24 +344,68 @@ __global__ __launch_bounds__(256) void k_frame_sums(State5 a, State5 b, int has_
     if (threadIdx.x < 8) part[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Sums the partials of k_frame_sums over workgroups in a fixed order.
-__global__ void k_frame_final(const double* __restrict__ part, int groups, double* __restrict__ out)
+// Sums the partials of k_frame_sums over workgroups in a fixed order: each
+// of 256 threads adds the groups g = t, t + 256, ... in turn, then a tree over
+// the threads; one pass for each of the first nout quantities.
+__global__ __launch_bounds__(256) void k_frame_final(const double* __restrict__ part, int groups, int nout,
+                                                     double* __restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= 8) return;
-    double s = 0.0;
-    for (int g = 0; g < groups; ++g) s += part[g * 8 + k];
-    out[k] = s;
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < nout; ++k) {
+        double s = 0.0;
+        for (int g = t; g < groups; g += 256) s += part[g * 8 + k];
+        red[t] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        if (t == 0) out[k] = red[0];
+        __syncthreads();
+    }
 }
 
 // ---- launchers ----
 
+template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
+static void conv_t(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
+                   int dil, int N, int H, int W, hipStream_t s)
+{
+    // a resident grid (3 waves per SIMD on 256 CUs) walks the segments, so
+    // each wave loads the weights once
+    const long long segs = (long long)N * H * (W / 32);
+    long long groups = (segs + 3) / 4;
+    if (groups > 768) groups = 768;
+    hipLaunchKernelGGL((k_conv<CIN, RELU, OUTF32, RES, MASK>), dim3((unsigned)groups), dim3(256), 0, s, in, w, bias, res,
+                       mask, out, dil, N, H, W);
+}
+
+template <int CIN, bool RELU, bool OUTF32>
+static void conv_rm(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
+                    int dil, int N, int H, int W, hipStream_t s)
+{
+    if (res && mask) conv_t<CIN, RELU, OUTF32, true, true>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else if (res) conv_t<CIN, RELU, OUTF32, true, false>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else if (mask) conv_t<CIN, RELU, OUTF32, false, true>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else conv_t<CIN, RELU, OUTF32, false, false>(in, w, bias, res, mask, out, dil, N, H, W, s);
+}
+
+template <int CIN>
+static void conv_c(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
+                   int out_f32, int relu_in, int dil, int N, int H, int W, hipStream_t s)
+{
+    if (relu_in && out_f32) conv_rm<CIN, true, true>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else if (relu_in) conv_rm<CIN, true, false>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else if (out_f32) conv_rm<CIN, false, true>(in, w, bias, res, mask, out, dil, N, H, W, s);
+    else conv_rm<CIN, false, false>(in, w, bias, res, mask, out, dil, N, H, W, s);
+}
+
 hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const void* res, const bf16* mask,
                 void* out, int out_f32, int relu_in, int dil, int N, int H, int W, hipStream_t s)
 {
-    const long long segs = (long long)N * H * (W / 32);
-    hipLaunchKernelGGL(k_conv, dim3((unsigned)((segs + 3) / 4)), dim3(256), 0, s, in, cin, w, bias, res, mask, out,
-                       out_f32, relu_in, dil, N, H, W);
+    if (cin == 8) conv_c<8>(in, w, bias, res, mask, out, out_f32, relu_in, dil, N, H, W, s);
+    else conv_c<32>(in, w, bias, res, mask, out, out_f32, relu_in, dil, N, H, W, s);
     return hipGetLastError();
 }
 
@@ -412,7 +477,7 @@ hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, c
 {
     const State5 bb = b ? *b : a;
     hipLaunchKernelGGL(k_frame_sums, dim3(groups), dim3(256), 0, s, a, bb, b != nullptr, npix, w, sc, part);
-    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(64), 0, s, part, groups, out);
+    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(256), 0, s, part, groups, b ? 8 : 1, out);
     return hipGetLastError();
 }
 

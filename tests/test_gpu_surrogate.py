@@ -248,11 +248,12 @@ def test_light_volume_and_judge(stream):
     h, w = 37, 64
     a, b = _rand_state(rng, h, w), _rand_state(rng, h, w)
     part = torch.empty(8 * 13, dtype=torch.float64, device="cuda")
-    out = torch.empty(8, dtype=torch.float64, device="cuda")
+    out = torch.full((8,), -7.0, dtype=torch.float64, device="cuda")
     sur.sur_light_volume(a["phi"], part, out[:1], stream)
     stream.synchronize()
     phi = a["phi"].double().cpu().numpy()
     assert abs(float(out[0]) - np.sum(0.5 * (1 - phi))) <= 1e-12 * np.sum(np.abs(phi)) * 10
+    assert torch.all(out[1:] == -7.0)       # exactly one value written
     sur.sur_judge(a, b, sc, part, out, stream)
     stream.synchronize()
     A = {k: v.double().cpu().numpy() for k, v in a.items()}
