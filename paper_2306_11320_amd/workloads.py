@@ -78,6 +78,24 @@ def heated_channel(lambda_ratio: float = 1.0, nx: int = 64, ny: int = 32, W: flo
     return p, f
 
 
+def heated_channel_table1(lambda_ratio: float = 1.0, W: float = 3.0) -> tuple[dict, dict]:
+    """The heated channel at the size of the paper's Table 1 (Sec. 4.1):
+    160 x 80 lattice, H = h = 40, lower wall T_h + T_0 cos(2 pi x / 160) with
+    T_h = 20, T_0 = 4, upper wall T_c = 10, T_ref = 10, sigma_T = -5e-4,
+    sigma_ref = 2.5e-2, rho = c_p = 1, mu = 0.2 in both fluids, lambda_h = 0.2,
+    lambda_l = 0.2 lambda_ratio; light fluid on top.  Starts from the flat
+    interface, u = 0 and the conduction profile between the wall means."""
+    nx, ny = 160, 80
+    Th, Tc, T0 = 20.0, 10.0, 4.0
+    p, f = heated_channel(lambda_ratio, nx=nx, ny=ny, W=W, T0=Tc, dT=T0)
+    p["tw_mean"] = [0.0, 0.0, Th, Tc]
+    p["T_ref"] = 10.0
+    j = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    f["T"] = Th + (Tc - Th) * (j + 0.5) / ny
+    p["meta"] = dict(Th=Th, Tc=Tc, T0=T0, H=40.0, h=40.0, L=float(nx), lambda_r=lambda_ratio)
+    return p, f
+
+
 # ---------------------------------------------------------------------------
 # Thermocapillary migration of a deformable droplet (Sec. 4.2)
 # ---------------------------------------------------------------------------
@@ -130,6 +148,31 @@ def droplet(Ma: float = 0.1, ratio: float = 1.0, nx: int = 256, ny: int = 1024, 
 # ---------------------------------------------------------------------------
 # Two recalcitrant bubbles with a parabolic sigma(T) (Sec. 4.3)
 # ---------------------------------------------------------------------------
+
+def droplet_table2(rho_ratio: float, nx: int = 160, ny: int = 320, R: float = 20.0) -> tuple[dict, dict]:
+    """The density-ratio test of Sec. 4.2 (Table 2): light drop of radius 20
+    at the centre of a 160 x 320 lattice, periodic in x, walls in y with the
+    linear temperature of |grad T| = 0.1 from T_c = 16 at the bottom,
+    rho_h = 1, rho_l = rho_h / rho_ratio, kinematic viscosity 0.8 in both
+    fluids, (rho c_p)_h = 5, (rho c_p)_l = 1, lambda_h = 0.2, lambda_l = 0.1,
+    sigma_ref = 2.5e-4, sigma_T = -1e-5 (the reading that reproduces every
+    U_YGB of Table 2)."""
+    gradT, Tc = 0.1, 16.0
+    cx, cy = nx / 2.0, ny / 2.0
+    nu = 0.8
+    p = base_params(nx, ny)
+    p.update(bc=[PERIODIC, PERIODIC, WALL_T, WALL_T], W=3.0,
+             rho_h=1.0, rho_l=1.0 / rho_ratio, mu_h=nu, mu_l=nu / rho_ratio,
+             lambda_h=0.2, lambda_l=0.1, rhocp_h=5.0, rhocp_l=1.0,
+             sigma_ref=2.5e-4, sigma_T=-1e-5, sigma_TT=0.0, T_ref=Tc + gradT * (cy + 0.5))
+    p["tw_mean"] = [0.0, 0.0, Tc, Tc + gradT * ny]
+    i, j = grid(nx, ny)
+    phi = tanh_profile(np.sqrt((i - cx) ** 2 + (j - cy) ** 2) - R, 3.0)
+    f = dict(phi=phi, ux=np.zeros_like(phi), uy=np.zeros_like(phi), T=Tc + gradT * (j + 0.5))
+    U = 1e-5 * gradT * R / nu
+    p["meta"] = dict(U=U, R=R, gradT=gradT, rho_r=rho_ratio, mu_r=1.0 / rho_ratio, lambda_r=0.5, cx=cx, cy=cy)
+    return p, f
+
 
 def bubble_positions(nx: int, ny: int, radii=(24.0, 32.0), seed: int = 3):
     rng = np.random.default_rng(seed)
