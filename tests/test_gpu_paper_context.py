@@ -1,0 +1,132 @@
+"""The GPU path at the sizes of the paper's own tests, with the paper's printed
+numbers as context (they come from the authors' runs, not from a closed form).
+
+* Table 1 (Sec. 4.1): heated channel 160 x 80, W = 3.  The GPU equals the FP64
+  oracle after 2000 steps (relative L2 <= 1e-10).  At steady state the
+  temperature error against the closed form is 2.0e-4 for lambda_r = 1 (the
+  paper prints 4.4e-4) and 1.0e-2 for lambda_r = 0.2 (paper 1.4e-3); the
+  velocity is 12 % below the sharp-interface closed form for either W = 3 or
+  1.5 (E_delta 0.14 / 0.11 for u_x / u_y, paper 0.037 / 0.045).
+* Table 2 (Sec. 4.2): the density-ratio droplet 160 x 320 for rho_r = 10 and
+  1000.  The terminal velocities land within 7 % of the circular-drop (2-D)
+  Stokes value U / (2 (1 + mu_r)(1 + lambda_r)) and 7-19 % below Eq. 60, the
+  sphere result that Table 2 compares with (paper: 2.4-4.4 % below).
+Bounds: the measured values with margins of 10-25 %.
+
+Parity at these sizes: the unit normal of the Allen-Cahn source is formed in
+the bulk too, where its defining vector (the moment vector, or grad phi) is at
+rounding level, so its direction there is set by rounding; the oracle and the
+GPU round differently (contracted multiply-adds), and the difference, scaled by
+the small counter term (1 - phi^2)/(sqrt2 W), grows slowly.  The checks are
+therefore one-step agreement of the populations (g and h to 1e-13 of their
+scale, f to 1e-6 absolute: the bulk counter term is ~1e-5 here) and agreement
+of the fields after many steps to 1e-4 (1e-3 at density ratio 1000; relative
+L2, u against its maximum).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_2306_11320_amd import workloads as wl
+from tests.conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_2306_11320_amd.lbm")
+
+TABLE1_PAPER = {1.0: dict(T=4.37e-4, ux=3.66e-2, uy=4.47e-2), 0.2: dict(T=1.40e-3, ux=6.08e-2, uy=7.00e-2)}
+TABLE2_PAPER = {10.0: 8.3296e-6, 100.0: 9.5978e-6, 500.0: 9.7345e-6, 1000.0: 9.7528e-6}
+
+
+def rel_l2(a, b):
+    return float(np.sqrt(np.sum((np.asarray(a) - np.asarray(b)) ** 2) / np.sum(np.asarray(b) ** 2)))
+
+
+def _one_step(o, lat):
+    o.step(1)
+    lat.step(1)
+    so, sg = o.get_state(), lat.get_state(0)
+    for k in ("g", "h"):
+        assert np.abs(sg[k] - so[k]).max() <= 1e-13 * np.abs(so[k]).max(), k
+    assert np.abs(sg["f"] - so["f"]).max() <= 1e-6
+
+
+def _fields_close(o, lat, tol):
+    ref, got = o.fields(), lat.fields()
+    for k in ("phi", "T"):
+        assert rel_l2(got[k], ref[k]) <= tol, (k, rel_l2(got[k], ref[k]))
+    umax = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max())
+    for k in ("ux", "uy"):
+        e = float(np.sqrt(np.mean((got[k] - ref[k]) ** 2)) / umax)
+        assert e <= tol, (k, e)
+
+
+def test_table1_size_matches_oracle():
+    cfg, f0 = wl.heated_channel_table1(0.2)
+    announce("table1_vs_oracle")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    _one_step(o, lat)
+    o.step(1999)
+    lat.step(1999)
+    _fields_close(o, lat, 1e-4)
+    lat.close()
+
+
+@pytest.mark.parametrize("lambda_r,bounds", [(1.0, dict(T=2.5e-4, ux=0.16, uy=0.13)),
+                                             (0.2, dict(T=1.2e-2, ux=0.21, uy=0.18))])
+def test_table1_context(lambda_r, bounds):
+    cfg, f0 = wl.heated_channel_table1(lambda_r)
+    announce("table1_context", lambda_r)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.step(40000)
+    M = lat.fields()
+    i, j = wl.grid(160, 80)
+    T, ux, uy, _ = cf.channel_solution(i, j - 39.5, L=160, H=40, h=40, Tc=10.0, Th=20.0, T0=4.0,
+                                       lambda_r=lambda_r, mu_r=1.0, sigma_T=-5e-4, mu_h=0.2)
+    got = dict(T=cf.rel_l2(M["T"], T), ux=cf.rel_l2(M["ux"], ux), uy=cf.rel_l2(M["uy"], uy))
+    print(f"lambda_r={lambda_r}: E_delta {got} (paper, Table 1: {TABLE1_PAPER[lambda_r]})", flush=True)
+    for k, b in bounds.items():
+        assert got[k] <= b, (k, got[k])
+    # the flow goes the right way with the right shape: amplitude within 20 %
+    for k, ref in (("ux", ux), ("uy", uy)):
+        a = float(np.sum(M[k] * ref) / np.sum(ref * ref))
+        assert 0.80 <= a <= 1.05, (k, a)
+    lat.close()
+
+
+@pytest.mark.parametrize("rho_r", [10.0, 1000.0])
+def test_table2_context(rho_r):
+    cfg, f0 = wl.droplet_table2(rho_r)
+    announce("table2_context", rho_r)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.step(100000)
+    d = lat.diagnostics(raise_unstable=True)
+    U = cf.u_char(-1e-5, 0.1, 20.0, 0.8)
+    mu_r = 1.0 / rho_r
+    u2d = cf.u_2d(U, mu_r, 0.5)
+    uygb = cf.u_ygb(U, mu_r, 0.5)
+    print(f"rho_r={rho_r}: U_r {d['u_r']:.4e}, 2-D theory {u2d:.4e}, Eq. 60 {uygb:.4e}, "
+          f"paper's U_r {TABLE2_PAPER[rho_r]:.4e}", flush=True)
+    assert abs(d["u_r"] / u2d - 1.0) <= 0.08
+    assert d["u_r"] < uygb
+    assert d["n_nonfinite"] == 0
+    lat.close()
+
+
+def test_high_density_ratio_matches_oracle():
+    """rho_r = 1000 on a small lattice: one step, then 500 steps and the drop's
+    velocity."""
+    cfg, f0 = wl.droplet_table2(1000.0, nx=48, ny=96, R=10.0)
+    announce("rho1000_vs_oracle")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    _one_step(o, lat)
+    o.step(499)
+    lat.step(499)
+    _fields_close(o, lat, 1e-3)
+    do, dg = o.diagnostics(), lat.diagnostics()
+    print(f"U_r oracle {do['u_r']:.6e} GPU {dg['u_r']:.6e}", flush=True)
+    assert abs(dg["u_r"] - do["u_r"]) <= 1e-3 * abs(do["u_r"])
+    lat.close()
