@@ -29,6 +29,13 @@
  *     destination node x + c_i and time t; the source term uses the source node;
  *   - isotropic D2Q9 stencils with mirror/Dirichlet ghosts for grad phi,
  *     lap phi and grad T (the paper does not say how they are discretised);
+ *   - collision of the NS and thermal LBEs: BGK as printed, or (collision = 1)
+ *     the two-relaxation-time variant the paper names as a simple extension
+ *     (Sec. 3): populations split into parts even and odd under c_i -> -c_i;
+ *     the part carrying the transport coefficient keeps the BGK time (even for
+ *     the viscosity of the NS LBE, odd for the conductivity of the thermal LBE),
+ *     the other one follows from (tau+ - 1/2)(tau- - 1/2) = trt_magic; each
+ *     part of the forcing term gets its own factor 1 - 1/(2 tau);
  *   - halfway bounce-back walls, anti-bounce-back Dirichlet temperature walls,
  *     bounce-back adiabatic walls; inlet: anti-bounce-back for phi and T and
  *     moving-wall bounce-back for the inflow velocity; outlet: anti-bounce-back
@@ -60,6 +67,9 @@ typedef struct {
     int32_t bc[4];      /* x-lo, x-hi, y-lo, y-hi */
     int32_t grad_mode;  /* 0: normal and grad T from moments; 1: from the stencils */
     int32_t n_bubbles;  /* number of tracked light-phase regions (<= 4) */
+    int32_t collision;  /* 0: BGK; 1: two-relaxation-time for the NS and thermal LBEs */
+    int32_t pad_;
+    double trt_magic;   /* (tau+ - 1/2)(tau- - 1/2) of the two-relaxation-time collision */
     double rho_l, rho_h, mu_l, mu_h, lam_l, lam_h, rcp_l, rcp_h;
     double sigma_ref, sigma_T, sigma_TT, T_ref;
     double W, M;
@@ -375,7 +385,7 @@ static void collide_stream(orc_state* S)
             }
             double Fhat = -rcp * (ux * tgx + uy * tgy);
 
-            double fs[9], gs[9], hs[9];
+            double fs[9], gs[9], hs[9], geq[9], Gi[9];
             for (int k = 0; k < 9; ++k) {
                 double cu = CX[k] * ux + CY[k] * uy;
                 /* Eq. 14 with source R_i */
@@ -384,15 +394,34 @@ static void collide_stream(orc_state* S)
 
                 /* NS LBE: equilibrium with s_i(u) and forcing G_i */
                 double si = WI[k] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
-                double geq = (k == 0 ? pr / CS2 * (WI[0] - 1.0) : pr / CS2 * WI[k]) + rho * si;
+                geq[k] = (k == 0 ? pr / CS2 * (WI[0] - 1.0) : pr / CS2 * WI[k]) + rho * si;
                 /* u grad rho : (c_i c_i - c_s^2 I) */
                 double tens = ux * grx * (CX[k] * CX[k] - CS2) + ux * gry * (CX[k] * CY[k])
                             + uy * grx * (CY[k] * CX[k]) + uy * gry * (CY[k] * CY[k] - CS2);
-                double Gi = WI[k] * (ugr + (CX[k] * Fx + CY[k] * Fy) / CS2 + tens / CS2);
-                gs[k] = gk[k] - (gk[k] - geq) / tau_g + (1.0 - 1.0 / (2.0 * tau_g)) * Gi;
-
-                /* Eq. 28 collision part: h_i - (h_i - h_i^eq)/tau_h + Fhat_i */
-                hs[k] = hk[k] - (hk[k] - WI[k] * T) / tau_h + WI[k] * Fhat;
+                Gi[k] = WI[k] * (ugr + (CX[k] * Fx + CY[k] * Fy) / CS2 + tens / CS2);
+            }
+            if (P->collision == 0) {
+                for (int k = 0; k < 9; ++k) {
+                    gs[k] = gk[k] - (gk[k] - geq[k]) / tau_g + (1.0 - 1.0 / (2.0 * tau_g)) * Gi[k];
+                    /* Eq. 28 collision part: h_i - (h_i - h_i^eq)/tau_h + Fhat_i */
+                    hs[k] = hk[k] - (hk[k] - WI[k] * T) / tau_h + WI[k] * Fhat;
+                }
+            } else {
+                /* two relaxation times: even part (+) and odd part (-) of each
+                   population, equilibrium and forcing term */
+                double tgp = tau_g, tgm = 0.5 + P->trt_magic / (tau_g - 0.5);
+                double thm = tau_h, thp = 0.5 + P->trt_magic / (tau_h - 0.5);
+                for (int k = 0; k < 9; ++k) {
+                    int kb = OPP[k];
+                    double gp = 0.5 * (gk[k] + gk[kb]), gm = 0.5 * (gk[k] - gk[kb]);
+                    double ep = 0.5 * (geq[k] + geq[kb]), em = 0.5 * (geq[k] - geq[kb]);
+                    double Gp = 0.5 * (Gi[k] + Gi[kb]), Gm = 0.5 * (Gi[k] - Gi[kb]);
+                    gs[k] = gk[k] - (gp - ep) / tgp - (gm - em) / tgm
+                          + (1.0 - 1.0 / (2.0 * tgp)) * Gp + (1.0 - 1.0 / (2.0 * tgm)) * Gm;
+                    double hp = 0.5 * (hk[k] + hk[kb]), hm = 0.5 * (hk[k] - hk[kb]);
+                    /* h_i^eq = w_i T and the source w_i Fhat are even */
+                    hs[k] = hk[k] - (hp - WI[k] * T) / thp - hm / thm + WI[k] * Fhat;
+                }
             }
             (void)rcp;
 

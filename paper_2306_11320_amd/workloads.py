@@ -33,8 +33,20 @@ def base_params(nx: int, ny: int) -> dict:
         sigma_ref=1e-3, sigma_T=0.0, sigma_TT=0.0, T_ref=0.0, W=3.0, mobility=0.1, Gx=0.0, Gy=0.0,
         tw_mean=[0.0] * 4, tw_amp=[0.0] * 4, tw_k=[0.0] * 4, tw_slope=[0.0] * 4,
         u_in_mean=0.0, phi_in=1.0, T_in=0.0, phi0_dev=0.0, T0_dev=0.0,
-        bubbles_x=[], bubbles_y=[],
+        bubbles_x=[], bubbles_y=[], collision=0, trt_magic=3.0 / 16.0,
     )
+
+
+def body_force_channel(ny: int = 32, mu: float = 0.5, G: float = 1e-6, collision: int = 0,
+                       trt_magic: float = 3.0 / 16.0, nx: int = 4) -> tuple[dict, dict]:
+    """One fluid (phi = 1 everywhere) between adiabatic no-slip walls at
+    j = -1/2 and ny - 1/2, periodic in x, driven by the body force G along x:
+    plane Poiseuille flow, u_x = G (y + 1/2)(ny - 1/2 - y) / (2 mu) at steady state."""
+    p = base_params(nx, ny)
+    p.update(bc=[PERIODIC, PERIODIC, WALL_ADIABATIC, WALL_ADIABATIC], mu_l=mu, mu_h=mu, Gx=G,
+             collision=collision, trt_magic=trt_magic)
+    phi = np.ones((ny, nx))
+    return p, dict(phi=phi, ux=np.zeros_like(phi), uy=np.zeros_like(phi), T=np.zeros_like(phi))
 
 
 def tanh_profile(d: np.ndarray, W: float) -> np.ndarray:
