@@ -41,7 +41,10 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
+
+/* Collision models (lbm_params.collision). */
+enum { LBM_BGK = 0, LBM_TRT = 1 };
 
 enum {
     LBM_OK = 0,
@@ -88,6 +91,10 @@ typedef struct lbm_params {
                               the thermal source from the local moments (Sec. 3.1,
                               Sec. 3.2); 1: both from the stencils */
     uint32_t n_bubbles;    /* light-phase regions tracked by lbm_diagnostics (0..4) */
+    uint32_t collision;    /* LBM_BGK: the single-relaxation-time collisions of Sec. 3;
+                              LBM_TRT: two relaxation times for the NS and thermal LBEs
+                              (the extension Sec. 3 names), see trt_magic */
+    uint32_t reserved;     /* must be 0 */
     /* fluid properties; _l: light (phi = -1), _h: heavy (phi = +1); each is
        interpolated linearly in phi (Sec. 4 preamble).  mu is the dynamic
        viscosity, lambda the conductivity, rhocp the heat capacitance rho*c_p. */
@@ -97,6 +104,10 @@ typedef struct lbm_params {
     double sigma_ref, sigma_T, sigma_TT, T_ref;
     double W;              /* interface width parameter (W = 3 in Sec. 4) */
     double mobility;       /* M_phi = c_s^2 (tau_phi - 1/2) */
+    double trt_magic;      /* LBM_TRT: (tau+ - 1/2)(tau- - 1/2); the part that carries the
+                              transport coefficient (even for the viscosity, odd for the
+                              conductivity) keeps the single-relaxation time; 3/16 makes
+                              halfway bounce-back exact for plane Poiseuille flow */
     double Gx, Gy;         /* uniform additional body force G of Eq. 7 */
     /* wall temperature along each side, s the coordinate along the wall:
        T_w(s) = Tw_mean + Tw_amp cos(Tw_k s) + Tw_slope s   (used by LBM_BC_WALL_T) */

@@ -66,6 +66,9 @@ int validate(const lbm_params& p)
     if ((p.bc[2] == LBM_BC_PERIODIC) != (p.bc[3] == LBM_BC_PERIODIC))
         return fail(LBM_EINVAL, "y sides: periodic paired with a non-periodic side");
     if (p.grad_mode > 1) return fail(LBM_EINVAL, "grad_mode must be 0 or 1");
+    if (p.collision != LBM_BGK && p.collision != LBM_TRT) return fail(LBM_EINVAL, "unknown collision %u", p.collision);
+    if (p.reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+    if (p.collision == LBM_TRT && !(p.trt_magic > 0)) return fail(LBM_EINVAL, "trt_magic must be positive");
     if (p.n_bubbles > 4) return fail(LBM_EINVAL, "at most 4 tracked regions");
     if (!(p.rho_l > 0 && p.rho_h > 0)) return fail(LBM_EINVAL, "densities must be positive");
     if (!(p.mu_l > 0 && p.mu_h > 0)) return fail(LBM_EINVAL, "viscosities must be positive (tau_g > 1/2)");
@@ -111,6 +114,8 @@ lbm::Inst<real> make_inst(const lbm_params& p, const Layout& L, char* ws)
     I.pitch = L.pitch;
     I.plane = L.plane;
     I.grad_mode = (int)p.grad_mode;
+    I.collision = (int)p.collision;
+    I.trt_magic = (real)p.trt_magic;
     for (int s = 0; s < 4; ++s) I.bc[s] = (int)p.bc[s];
     const double phi0 = p.phi0_dev, T0 = p.T0_dev;
     I.phi0 = (real)phi0;

@@ -22,6 +22,8 @@ struct Inst {
     real* pop[2];        // time levels A and B
     real* jprev;         // 2 planes: (phi u)_x, (phi u)_y of the previous level
     int nx, ny, pitch, grad_mode;
+    int collision;       // 0: BGK; 1: two relaxation times for g and h
+    real trt_magic;      // (tau+ - 1/2)(tau- - 1/2)
     long long plane;
     int bc[4];
     real phi0, T0;

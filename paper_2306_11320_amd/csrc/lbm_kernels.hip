@@ -329,7 +329,7 @@ __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, unsigned
     return false;
 }
 
-template <typename real, int TX, int TY, bool EDGE>
+template <typename real, int TX, int TY, bool EDGE, bool TRT>
 __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
 {
     using PT = Patch<real, TX, TY>;
@@ -367,6 +367,15 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
     const real fac_g = real(1) - real(0.5) * inv_tau_g;
     const real tau_h = real(0.5) + real(3) * lam;
     const real inv_tau_h = recip(tau_h);
+    // two relaxation times: (tau+ - 1/2)(tau- - 1/2) = trt_magic; the NS LBE's
+    // even part and the thermal LBE's odd part keep the times above
+    real inv_tau_gm = 0, fac_gm = 0, inv_tau_hp = 0;
+    if (TRT) {
+        const real tau_g = real(1) / inv_tau_g;
+        inv_tau_gm = recip(real(0.5) + I.trt_magic * recip(tau_g - real(0.5)));
+        fac_gm = real(1) - real(0.5) * inv_tau_gm;
+        inv_tau_hp = recip(real(0.5) + I.trt_magic * recip(tau_h - real(0.5)));
+    }
 
     // time derivative of phi u by the first-order Euler scheme; store phi u
     const real jx = phi * ux, jy = phi * uy;
@@ -438,7 +447,18 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
         const real cF = real(cx(k)) * m.Fx + real(cy(k)) * m.Fy;
         const real cg = real(cx(k)) * m.grx + real(cy(k)) * m.gry;
         const real Gi = w * real(3) * (cF + cu * cg);
-        const real gsk = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
+        real gsk;
+        if (!TRT) {
+            gsk = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
+        } else {
+            // even and odd parts under c_i -> -c_i of g_i, g_i^eq and G_i
+            const int kb = opp(k);
+            const real gp = real(0.5) * (g[k] + g[kb]), gm = real(0.5) * (g[k] - g[kb]);
+            const real ep = (k == 0 ? p3 * (w - real(1)) : p3 * w) + m.rho * w * (real(4.5) * cu * cu - real(1.5) * uu);
+            const real em = m.rho * w * real(3) * cu;
+            const real Gp = w * real(3) * (cu * cg), Gm = w * real(3) * cF;
+            gsk = g[k] - (gp - ep) * inv_tau_g - (gm - em) * inv_tau_gm + fac_g * Gp + fac_gm * Gm;
+        }
         real fsk, hsk;
         if (k == 0) {
             fsk = f[0] + df;
@@ -448,8 +468,15 @@ __device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, P
             const real feq = w * (m.dphi + real(3) * phi * cu);
             const real Ri = w * (real(cx(k)) * ax + real(cy(k)) * ay);
             fsk = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
-            // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat
-            hsk = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
+            // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat; with two
+            // relaxation times the odd part (conduction) keeps tau_h
+            if (!TRT) {
+                hsk = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
+            } else {
+                const int kb = opp(k);
+                const real hp = real(0.5) * (h[k] + h[kb]), hm = real(0.5) * (h[k] - h[kb]);
+                hsk = h[k] - (hp - w * theta) * inv_tau_hp - hm * inv_tau_h + w * Fhat;
+            }
             df += f[k] - fsk;
             dh += h[k] - hsk;
         }
@@ -518,8 +545,15 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
     my_tiles(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
         const Tile tl = tiles[t];
-        if (tl.flags & kTileInterior) tile_step<real, TX, TY, false>(insts[tl.inst], tl.x0, tl.y0, src, S);
-        else tile_step<real, TX, TY, true>(insts[tl.inst], tl.x0, tl.y0, src, S);
+        const Inst<real>& I = insts[tl.inst];
+        const bool interior = tl.flags & kTileInterior;
+        if (I.collision == 0) {
+            if (interior) tile_step<real, TX, TY, false, false>(I, tl.x0, tl.y0, src, S);
+            else tile_step<real, TX, TY, true, false>(I, tl.x0, tl.y0, src, S);
+        } else {
+            if (interior) tile_step<real, TX, TY, false, true>(I, tl.x0, tl.y0, src, S);
+            else tile_step<real, TX, TY, true, true>(I, tl.x0, tl.y0, src, S);
+        }
         if (t + 1 < t1) __syncthreads();
     }
 }

@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_DEV = 0, 1
@@ -44,10 +44,12 @@ class Params(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("nx", C.c_uint32), ("ny", C.c_uint32), ("precision", C.c_uint32),
         ("bc", C.c_uint32 * 4), ("grad_mode", C.c_uint32), ("n_bubbles", C.c_uint32),
+        ("collision", C.c_uint32), ("reserved", C.c_uint32),
         ("rho_l", C.c_double), ("rho_h", C.c_double), ("mu_l", C.c_double), ("mu_h", C.c_double),
         ("lambda_l", C.c_double), ("lambda_h", C.c_double), ("rhocp_l", C.c_double), ("rhocp_h", C.c_double),
         ("sigma_ref", C.c_double), ("sigma_T", C.c_double), ("sigma_TT", C.c_double), ("T_ref", C.c_double),
-        ("W", C.c_double), ("mobility", C.c_double), ("Gx", C.c_double), ("Gy", C.c_double),
+        ("W", C.c_double), ("mobility", C.c_double), ("trt_magic", C.c_double), ("Gx", C.c_double),
+        ("Gy", C.c_double),
         ("Tw_mean", C.c_double * 4), ("Tw_amp", C.c_double * 4), ("Tw_k", C.c_double * 4),
         ("Tw_slope", C.c_double * 4),
         ("u_in_mean", C.c_double), ("phi_in", C.c_double), ("T_in", C.c_double),
@@ -142,6 +144,8 @@ def make_params(cfg: dict, precision: int = FP64) -> Params:
         p.Tw_k[s] = float(cfg.get("tw_k", [0.0] * 4)[s])
         p.Tw_slope[s] = float(cfg.get("tw_slope", [0.0] * 4)[s])
     p.grad_mode = int(cfg.get("grad_mode", 0))
+    p.collision = int(cfg.get("collision", 0))
+    p.trt_magic = float(cfg.get("trt_magic", 3.0 / 16.0))
     bx, by = list(cfg.get("bubbles_x", [])), list(cfg.get("bubbles_y", []))
     p.n_bubbles = len(bx)
     for b in range(len(bx)):

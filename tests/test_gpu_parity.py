@@ -166,3 +166,48 @@ def test_checkpoint_resume_bitwise():
     for k in ("f", "g", "h", "jprev"):
         assert np.array_equal(sa[k], sb[k]), k
     assert sb["step"] == 71
+
+
+# ---- two-relaxation-time collision -------------------------------------------
+
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[0], wl.ALL_BCS[1], wl.ALL_BCS[4]], ids=["periodic", "channel", "inlet"])
+@pytest.mark.parametrize("magic", [3.0 / 16.0, 0.25])
+def test_one_step_trt_fp64(bcs, magic):
+    cfg, f0 = wl.tiny(70, 13, bc=bcs, seed=17)
+    cfg.update(collision=1, trt_magic=magic)
+    announce("one_step_trt", bcs, magic)
+    o, st = perturbed_state(cfg, f0, seed=8)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.set_state(0, **st, step=0)
+    o.step(1)
+    lat.step(1)
+    compare_pops(lat.get_state(), o.get_state(), ONE_STEP_TOL)
+
+
+def test_multistep_trt_fp64():
+    cfg, f0 = wl.tiny(96, 72, bc=wl.ALL_BCS[1], seed=6)
+    cfg.update(collision=1)
+    announce("multistep_trt")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    o.step(300)
+    lat.step(300)
+    ref, got = o.fields(), lat.fields()
+    for k in ("phi", "ux", "uy", "T", "p"):
+        e = rel_l2(got[k], ref[k])
+        assert e <= MULTI_STEP_TOL, f"{k}: rel L2 {e:.3e}"
+
+
+@pytest.mark.parametrize("prec,tol", [(lbm.FP64, 1e-12), (lbm.FP32_DEV, 1e-4)], ids=["fp64", "fp32dev"])
+def test_trt_poiseuille_exact(prec, tol):
+    """The GPU reproduces the exactness of the two-relaxation-time collision
+    (magic 3/16) for plane Poiseuille flow that pins the oracle."""
+    ny, mu, G = 32, 0.5, 1e-6
+    cfg, f0 = wl.body_force_channel(ny, mu, G, collision=1, nx=64)
+    announce("trt_poiseuille", prec)
+    lat = lbm.Lattice(cfg, f0, prec)
+    lat.step(40000)
+    ux = lat.fields()["ux"]
+    y = np.arange(ny)
+    exact = G / (2 * mu) * (y + 0.5) * (ny - 0.5 - y)
+    assert np.abs(ux - exact[:, None]).max() <= tol * exact.max()
