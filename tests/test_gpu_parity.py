@@ -211,3 +211,17 @@ def test_trt_poiseuille_exact(prec, tol):
     y = np.arange(ny)
     exact = G / (2 * mu) * (y + 0.5) * (ny - 0.5 - y)
     assert np.abs(ux - exact[:, None]).max() <= tol * exact.max()
+
+
+def test_full_size_bubbles_one_step_fp64():
+    """One step at the two-bubble workload's full size (512 x 2048, walls in x,
+    inflow and outflow in y, parabolic sigma(T), density ratio 10) from a
+    perturbed equilibrium, every population compared."""
+    cfg, f0 = wl.two_bubbles(sigma_TT=0.2)
+    announce("full_size_bubbles_one_step", cfg["nx"], cfg["ny"])
+    o, st = perturbed_state(cfg, f0, seed=4)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.set_state(0, **st, step=0)
+    o.step(1)
+    lat.step(1)
+    compare_pops(lat.get_state(), o.get_state(), ONE_STEP_TOL)

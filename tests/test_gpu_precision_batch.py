@@ -245,3 +245,33 @@ def test_reinit_shift_keeps_non_equilibrium(prec):
     want = WGT[:, None, None] * dT * np.ones_like(d)
     assert np.allclose(d, want, rtol=0, atol=1e-15 if prec == lbm.FP64 else 2e-7)
     lat.close()
+
+
+def test_fp32_dev_full_bubbles():
+    """The two-bubble workload at full size (512 x 2048) in FP32 deviation
+    storage against the FP64 oracle after 300 steps."""
+    cfg, f0 = wl.two_bubbles(sigma_TT=0.2)
+    announce("fp32_dev_full_bubbles")
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    o.step(300)
+    lat.step(300)
+    check_fp32(lat.fields(), o.fields(), cfg["T_ref"])
+
+
+def test_sweep_full_batch_sampled():
+    """The 64-lattice sweep (9.79 M nodes) in the launch configuration the
+    benchmark times (one batched launch per step, autotuned tile and grid):
+    three lattices sampled across the batch against the FP64 oracle run alone."""
+    items = wl.sweep(64, seed=4)
+    announce("sweep_full_batch", len(items))
+    lat = lbm.Lattice.batch(items, lbm.FP32_DEV)
+    lat.autotune(steps_per_trial=4)
+    done = lat.get_state(0)["step"]
+    lat.step(100 - done if done < 100 else 0)
+    steps = max(done, 100)
+    for k in (0, 31, 63):
+        cfg, f0 = items[k]
+        o = oracle.Oracle(cfg, f0)
+        o.step(steps)
+        check_fp32(lat.fields(k), o.fields(), cfg["T_ref"])
