@@ -55,22 +55,24 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     const long long nseg = (long long)N * H * segs_per_row;
     const long long wave0 = (long long)blockIdx.x * 4 + threadIdx.x / 64;
     const long long nwaves = (long long)gridDim.x * 4;
-    if (wave0 >= nseg) return;
     const int m = lane % 32, kh = lane / 32;
-    // the weight operands of the whole K loop stay in registers while the
-    // wave walks its 32-pixel segments
-    bf16x8 b[NKB];
-#pragma unroll
-    for (int q = 0; q < NKB; ++q) {
-        const int kk = q * 16 + 8 * kh;
-        const bool kv = kk < K;
-        const int kc = kv ? kk : 0;
-        b[q] = load8(w + ((long long)m * 9 + kc / CIN) * CIN + kc % CIN);  // column co = lane % 32
-        if (!kv) b[q] = bf16x8{};
+    // the weight operands of the whole K loop are staged once per workgroup
+    // in LDS, in the order the lanes read them
+    __shared__ bf16x8 sB[NKB][64];
+    for (int e = threadIdx.x; e < NKB * 64; e += blockDim.x) {
+        const int q = e / 64, l = e % 64;
+        const int kk = q * 16 + 8 * (l / 32);
+        bf16x8 v = bf16x8{};
+        if (kk < K) v = load8(w + ((long long)(l % 32) * 9 + kk / CIN) * CIN + kk % CIN);  // column co = l % 32
+        sB[q][l] = v;
     }
+    __syncthreads();
     const int co = lane % 32;
     const float bv = bias ? bias[co] : 0.f;
     for (long long seg = wave0; seg < nseg; seg += nwaves) {
+        // an index the compiler cannot hoist: the weight operands are read from
+        // LDS per segment instead of being held in 72 registers
+        const int lz = lane + 64 * (int)__builtin_amdgcn_readfirstlane((unsigned)(seg >> 40));
         const int x0 = (int)(seg % segs_per_row) * 32;
         const long long ny = seg / segs_per_row;
         const int y = (int)(ny % H), n = (int)(ny / H);
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
         f32x16 acc = {};
 #pragma unroll
         for (int q = 0; q < NKB; ++q)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], b[q], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
         const long long row = ((long long)n * H + y) * W;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -372,11 +374,11 @@ template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
 static void conv_t(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
                    int dil, int N, int H, int W, hipStream_t s)
 {
-    // a resident grid (3 waves per SIMD on 256 CUs) walks the segments, so
-    // each wave loads the weights once
+    // a resident grid (6 waves per SIMD on 256 CUs) walks the segments, so
+    // each workgroup stages the weights once
     const long long segs = (long long)N * H * (W / 32);
     long long groups = (segs + 3) / 4;
-    if (groups > 768) groups = 768;
+    if (groups > 1536) groups = 1536;
     hipLaunchKernelGGL((k_conv<CIN, RELU, OUTF32, RES, MASK>), dim3((unsigned)groups), dim3(256), 0, s, in, w, bias, res,
                        mask, out, dil, N, H, W);
 }
