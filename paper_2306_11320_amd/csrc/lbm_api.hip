@@ -175,6 +175,7 @@ struct lbm_ctx {
     int tile = 0;
     int graph_steps = 64;
     int grid = 0;
+    int any_trt = 0;  // some lattice relaxes with two relaxation times
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -242,7 +243,7 @@ void drop_graph(lbm_ctx* c)
 int launch_one(lbm_ctx* c, int src)
 {
     HIP_TRY(lbm::launch_step((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile], c->ntiles[c->tile], c->grid, src,
-                             c->stream));
+                             c->any_trt, c->stream));
     return LBM_OK;
 }
 
@@ -293,6 +294,8 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     c->ws = static_cast<char*>(d_ws);
     c->ws_bytes = ws_bytes;
     c->params.assign(ps, ps + n);
+    for (int k = 0; k < n; ++k)
+        if (ps[k].collision == LBM_TRT) c->any_trt = 1;
     c->lay = lay;
     c->grid = n > 1 ? -1 : 0;  // batched: persistent grid sized at the first step
     c->d_insts = c->ws + off_insts;
@@ -804,7 +807,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
         int grids[3] = {0, 0, 0}, ng = 1;
         if (c->n > 1) {
             int per_cu = 1;
-            if (lbm::step_occupancy((int)c->prec, t, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+            if (lbm::step_occupancy((int)c->prec, t, c->any_trt, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
             const int resident = per_cu * (cus > 0 ? cus : 256);
             grids[0] = resident < c->ntiles[t] ? resident : c->ntiles[t];
             grids[1] = 2 * resident < c->ntiles[t] ? 2 * resident : c->ntiles[t];

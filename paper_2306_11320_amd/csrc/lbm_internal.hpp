@@ -69,6 +69,7 @@ constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4};
 
 // Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
+                       int any_trt,
                        hipStream_t s);
 // Macroscopic fields of level `src`: any output may be null; out_f32 selects
 // float outputs.  If `jprev_out` is set, (phi u) is written to the lattice's
@@ -90,7 +91,7 @@ hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles,
                        const DiagArgs& a, double* partials, double* result, hipStream_t s);
 
 // Resident workgroups of the step kernel per compute unit.
-hipError_t step_occupancy(int prec, int tile, int* blocks_per_cu);
+hipError_t step_occupancy(int prec, int tile, int any_trt, int* blocks_per_cu);
 
 // Plain 16-byte-vector copy of `bytes` (a multiple of 16).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

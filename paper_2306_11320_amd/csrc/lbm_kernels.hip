@@ -330,7 +330,7 @@ __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, unsigned
 }
 
 template <typename real, int TX, int TY, bool EDGE, bool TRT>
-__device__ inline void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
+__device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
 {
     using PT = Patch<real, TX, TY>;
     constexpr int PX = PT::PX;
@@ -536,7 +536,9 @@ __device__ inline void my_tiles(int ntiles, int& t0, int& t1)
     t1 = (int)((long long)(L + 1) * ntiles / G);
 }
 
-template <typename real, int TX, int TY>
+// ANY_TRT: some lattice of the launch uses two relaxation times (a separate
+// kernel, so that the BGK-only kernel keeps its own register budget).
+template <typename real, int TX, int TY, bool ANY_TRT>
 __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
                                                   int ntiles, int src)
 {
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
         const Tile tl = tiles[t];
         const Inst<real>& I = insts[tl.inst];
         const bool interior = tl.flags & kTileInterior;
-        if (I.collision == 0) {
+        if (!ANY_TRT || I.collision == 0) {
             if (interior) tile_step<real, TX, TY, false, false>(I, tl.x0, tl.y0, src, S);
             else tile_step<real, TX, TY, true, false>(I, tl.x0, tl.y0, src, S);
         } else {
@@ -831,11 +833,16 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 // ---- launchers ----
 
 template <typename real, int TX, int TY>
-static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, hipStream_t s)
+static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, int any_trt,
+                         hipStream_t s)
 {
     const int G = grid > 0 ? grid : ntiles;
-    hipLaunchKernelGGL((k_step<real, TX, TY>), dim3(G), dim3(TX * TY), 0, s, static_cast<const Inst<real>*>(insts),
-                       tiles, ntiles, src);
+    if (any_trt)
+        hipLaunchKernelGGL((k_step<real, TX, TY, true>), dim3(G), dim3(TX * TY), 0, s,
+                           static_cast<const Inst<real>*>(insts), tiles, ntiles, src);
+    else
+        hipLaunchKernelGGL((k_step<real, TX, TY, false>), dim3(G), dim3(TX * TY), 0, s,
+                           static_cast<const Inst<real>*>(insts), tiles, ntiles, src);
     return hipGetLastError();
 }
 
@@ -873,10 +880,10 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     }
 
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
-                       hipStream_t s)
+                       int any_trt, hipStream_t s)
 {
-#define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, s)
-#define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, s)
+#define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, any_trt, s)
+#define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, any_trt, s)
     if (prec == 0) { LBM_TILE_SWITCH(tile, STEP64) }
     LBM_TILE_SWITCH(tile, STEP32)
 #undef STEP64
@@ -884,15 +891,16 @@ hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles,
 }
 
 template <typename real, int TX, int TY>
-static hipError_t occ_t(int* blocks)
+static hipError_t occ_t(int* blocks, int any_trt)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY>, TX * TY, 0);
+    if (any_trt) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, true>, TX * TY, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, false>, TX * TY, 0);
 }
 
-hipError_t step_occupancy(int prec, int tile, int* blocks_per_cu)
+hipError_t step_occupancy(int prec, int tile, int any_trt, int* blocks_per_cu)
 {
-#define O64(a, b) occ_t<double, a, b>(blocks_per_cu)
-#define O32(a, b) occ_t<float, a, b>(blocks_per_cu)
+#define O64(a, b) occ_t<double, a, b>(blocks_per_cu, any_trt)
+#define O32(a, b) occ_t<float, a, b>(blocks_per_cu, any_trt)
     if (prec == 0) { LBM_TILE_SWITCH(tile, O64) }
     LBM_TILE_SWITCH(tile, O32)
 #undef O64
