@@ -109,6 +109,10 @@ lbm::Inst<real> make_inst(const lbm_params& p, const Layout& L, char* ws)
     I.pop[0] = reinterpret_cast<real*>(ws + L.pop_off[0]);
     I.pop[1] = reinterpret_cast<real*>(ws + L.pop_off[1]);
     I.jprev = reinterpret_cast<real*>(ws + L.jprev_off);
+    for (int l = 0; l < 2; ++l)
+        for (int q = 0; q < 27; ++q) I.qbase[l][q] = I.pop[l] + (size_t)q * (size_t)L.plane;
+    I.jbase[0] = I.jprev;
+    I.jbase[1] = I.jprev + L.plane;
     I.nx = L.nx;
     I.ny = L.ny;
     I.pitch = L.pitch;

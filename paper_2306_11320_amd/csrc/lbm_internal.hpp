@@ -21,6 +21,11 @@ template <typename real>
 struct Inst {
     real* pop[2];        // time levels A and B
     real* jprev;         // 2 planes: (phi u)_x, (phi u)_y of the previous level
+    // Base of population plane q of each level (pop[l] + q * plane) and of the
+    // two (phi u) planes: the step kernel reads them as uniform values instead
+    // of forming 64-bit products per plane.
+    real* qbase[2][27];
+    real* jbase[2];
     int nx, ny, pitch, grad_mode;
     int collision;       // 0: BGK; 1: two relaxation times for g and h
     real trt_magic;      // (tau+ - 1/2)(tau- - 1/2)

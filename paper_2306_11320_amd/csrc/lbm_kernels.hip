@@ -45,15 +45,17 @@ __device__ inline bool has_direction(double n2) { return n2 > 0.0; }
 // Node offsets within a population plane are 32-bit (the host checks that a
 // plane holds fewer than 2^29 nodes); the plane base is uniform, so loads and
 // stores take a scalar base and a 32-bit vector offset.
-// Base of population plane q: the same in every lane, and made a scalar
-// value so that the compiler keeps it in scalar registers.
-template <typename T>
-__device__ inline gptr<T> plane_of(gptr<T> base, int q, long long plane)
+// Base of population plane q of time level `lev`, read from the lattice's
+// parameter block (a scalar load).
+template <typename real>
+__device__ inline gptr<const real> src_plane(const Inst<real>& I, int lev, int q)
 {
-    const unsigned long long v = (unsigned long long)(base + (size_t)q * (size_t)plane);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+    return to_global<const real>(I.qbase[lev][q]);
+}
+template <typename real>
+__device__ inline gptr<real> dst_plane(const Inst<real>& I, int lev, int q)
+{
+    return to_global(I.qbase[lev][q]);
 }
 // Element at a 32-bit byte offset from a (uniform) base.
 template <typename T>
@@ -156,7 +158,7 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 template <typename real, int TX, int TY, bool EDGE>
-__device__ inline void fill_entry(const Inst<real>& I, gptr<const real> __restrict__ A, Patch<real, TX, TY>& S, int q,
+__device__ inline void fill_entry(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int q,
                                   int gx, int gy)
 {
     int sx, sy;
@@ -173,13 +175,13 @@ __device__ inline void fill_entry(const Inst<real>& I, gptr<const real> __restri
     real sf = 0, sh = 0, hk[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        sf += ld(plane_of(A, kF + k, I.plane), idx * (unsigned)sizeof(real));
-        hk[k] = ld(plane_of(A, kH + k, I.plane), idx * (unsigned)sizeof(real));
+        sf += ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
+        hk[k] = ld(src_plane(I, src, kH + k), idx * (unsigned)sizeof(real));
         sh += hk[k];
     }
-    const real dphi = EDGE ? aphi + sphi * sf : sf;
+    const real dphi = (EDGE && !rn) ? aphi + sphi * sf : sf;
     S.phi[q] = dphi;
-    S.T[q] = EDGE ? aT + sT * sh : sh;
+    S.T[q] = (EDGE && !rn) ? aT + sT * sh : sh;
     S.irc[q] = recip(I.rcp_a + I.rcp_b * (I.phi0 + dphi));
 #pragma unroll
     for (int k = 0; k < 9; ++k) S.h[k][q] = rn ? hk[k] : real(0);
@@ -189,7 +191,7 @@ __device__ inline void fill_entry(const Inst<real>& I, gptr<const real> __restri
 // Loads the work-item's own node and fills the patch.  Returns whether the
 // work-item's node lies in the lattice.
 template <typename real, int TX, int TY, bool EDGE>
-__device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restrict__ A, Patch<real, TX, TY>& S, int x0,
+__device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int x0,
                                   int y0, real (&f)[9], real (&g)[9], real (&h)[9])
 {
     using PT = Patch<real, TX, TY>;
@@ -203,9 +205,9 @@ __device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restri
         real sf = 0, sh = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = ld(plane_of(A, kF + k, I.plane), idx * (unsigned)sizeof(real));
-            h[k] = ld(plane_of(A, kH + k, I.plane), idx * (unsigned)sizeof(real));
-            g[k] = ld(plane_of(A, kG + k, I.plane), idx * (unsigned)sizeof(real));
+            f[k] = ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
+            h[k] = ld(src_plane(I, src, kH + k), idx * (unsigned)sizeof(real));
+            g[k] = ld(src_plane(I, src, kG + k), idx * (unsigned)sizeof(real));
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -218,7 +220,7 @@ __device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restri
 #pragma unroll
         for (int k = 0; k < 9; ++k) S.h[k][c] = h[k];
     } else {
-        fill_entry<real, TX, TY, EDGE>(I, A, S, c, gi, gj);
+        fill_entry<real, TX, TY, EDGE>(I, src, S, c, gi, gj);
     }
     for (int q = tid; q < PT::NRING; q += TX * TY) {
         int hx, hy;
@@ -229,7 +231,7 @@ __device__ inline bool load_patch(const Inst<real>& I, gptr<const real> __restri
             hx = r < TY ? -1 : TX;
             hy = r < TY ? r : r - TY;
         }
-        fill_entry<real, TX, TY, EDGE>(I, A, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
+        fill_entry<real, TX, TY, EDGE>(I, src, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
     }
     __syncthreads();
     return inside;
@@ -329,59 +331,46 @@ __device__ inline bool dest(const Inst<real>& I, int gi, int gj, int k, unsigned
     return false;
 }
 
-template <typename real, int TX, int TY, bool EDGE, bool TRT>
-__device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
-{
-    using PT = Patch<real, TX, TY>;
-    constexpr int PX = PT::PX;
-    const gptr<const real> __restrict__ A = to_global<const real>(I.pop[src]);
-    const gptr<real> __restrict__ B = to_global(I.pop[src ^ 1]);
-    const gptr<real> __restrict__ J = to_global(I.jprev);
-    real f[9], g[9], h[9];
-    const bool inside = load_patch<real, TX, TY, EDGE>(I, A, S, x0, y0, f, g, h);
-    if (!inside) return;
-    const int tid = threadIdx.x;
-    const int gi = x0 + tid % TX, gj = y0 + tid / TX;
-    const int c = (tid / TX + 1) * PX + (tid % TX + 1);
-    const long long P = I.plane;
-    const unsigned own = (unsigned)(gj * I.pitch + gi);
-    const real jpx = ld(plane_of(J, 0, P), own * (unsigned)sizeof(real)), jpy = ld(plane_of(J, 1, P), own * (unsigned)sizeof(real));
-    // destination rows and columns of the interior path (periodic wrap only)
-    unsigned drow[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
-    if (!EDGE) {
-        drow[0] = (unsigned)(wrap1(gj - 1, I.ny) * I.pitch);
-        drow[1] = (unsigned)(gj * I.pitch);
-        drow[2] = (unsigned)(wrap1(gj + 1, I.ny) * I.pitch);
-        dcol[0] = (unsigned)wrap1(gi - 1, I.nx);
-        dcol[1] = (unsigned)gi;
-        dcol[2] = (unsigned)wrap1(gi + 1, I.nx);
-    }
+// Collision quantities of one node beyond its macros.
+template <typename real>
+struct Pre {
+    real inv_tau_g, fac_g, inv_tau_h, inv_tau_gm, fac_gm, inv_tau_hp;
+    real ax, ay;  // R_i = w_i c_i . (ax, ay)
+    real Fhat, uu, p3;
+};
 
-    const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
+// Relaxation rates, the Allen-Cahn source vector and the thermal source of a
+// node; jx, jy return phi u, the next level's previous value.
+template <typename real, bool TRT>
+__device__ __forceinline__ Pre<real> pre_collide(const Inst<real>& I, const Macro<real>& m, const real (&f)[9],
+                                                 const real (&h)[9], real jpx, real jpy, real& jx, real& jy)
+{
+    Pre<real> q;
     const real phi = m.phi, ux = m.ux, uy = m.uy;
     const real mu = I.mu_a + I.mu_b * phi;
     const real lam = I.lam_a + I.lam_b * phi;
     const real rcp = I.rcp_a + I.rcp_b * phi;
     // mu = rho c_s^2 (tau_g - 1/2), lambda = c_s^2 (tau_h - 1/2)
-    const real inv_tau_g = m.rho * recip(real(0.5) * m.rho + real(3) * mu);
-    const real fac_g = real(1) - real(0.5) * inv_tau_g;
+    q.inv_tau_g = m.rho * recip(real(0.5) * m.rho + real(3) * mu);
+    q.fac_g = real(1) - real(0.5) * q.inv_tau_g;
     const real tau_h = real(0.5) + real(3) * lam;
-    const real inv_tau_h = recip(tau_h);
+    q.inv_tau_h = recip(tau_h);
     // two relaxation times: (tau+ - 1/2)(tau- - 1/2) = trt_magic; the NS LBE's
     // even part and the thermal LBE's odd part keep the times above
-    real inv_tau_gm = 0, fac_gm = 0, inv_tau_hp = 0;
+    q.inv_tau_gm = 0;
+    q.fac_gm = 0;
+    q.inv_tau_hp = 0;
     if (TRT) {
-        const real tau_g = real(1) / inv_tau_g;
-        inv_tau_gm = recip(real(0.5) + I.trt_magic * recip(tau_g - real(0.5)));
-        fac_gm = real(1) - real(0.5) * inv_tau_gm;
-        inv_tau_hp = recip(real(0.5) + I.trt_magic * recip(tau_h - real(0.5)));
+        const real tau_g = real(1) / q.inv_tau_g;
+        q.inv_tau_gm = recip(real(0.5) + I.trt_magic * recip(tau_g - real(0.5)));
+        q.fac_gm = real(1) - real(0.5) * q.inv_tau_gm;
+        q.inv_tau_hp = recip(real(0.5) + I.trt_magic * recip(tau_h - real(0.5)));
     }
 
-    // time derivative of phi u by the first-order Euler scheme; store phi u
-    const real jx = phi * ux, jy = phi * uy;
+    // time derivative of phi u by the first-order Euler scheme
+    jx = phi * ux;
+    jy = phi * uy;
     const real djx = jx - jpx, djy = jy - jpy;
-    st(plane_of(J, 0, P), own * (unsigned)sizeof(real), jx);
-    st(plane_of(J, 1, P), own * (unsigned)sizeof(real), (real)(jy));
 
     // Allen-Cahn source: unit normal from v = sum c_i (f_i - f_i^eq) + dt(phi u)/2, n = -v/|v|
     real nxv = 0, nyv = 0;
@@ -404,82 +393,116 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
     }
     const real pm1 = (I.phi0 - real(1)) + m.dphi;
     const real lamc = -pm1 * (phi + real(1)) * I.inv_s2W;  // (1 - phi^2)/(sqrt2 W)
-    const real ax = real(3) * djx + lamc * nxv;               // R_i = w_i c_i . (3 dt(phi u) + lamc n)
-    const real ay = real(3) * djy + lamc * nyv;
+    q.ax = real(3) * djx + lamc * nxv;                      // R_i = w_i c_i . (3 dt(phi u) + lamc n)
+    q.ay = real(3) * djy + lamc * nyv;
 
     // thermal source: grad T from the first moment of h (or the stencil), Fhat = -rho c_p u . grad T
     real tgx, tgy;
     if (I.grad_mode == 0) {
         const real hx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
         const real hy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-        tgx = real(-3) * hx * inv_tau_h;
-        tgy = real(-3) * hy * inv_tau_h;
+        tgx = real(-3) * hx * q.inv_tau_h;
+        tgy = real(-3) * hy * q.inv_tau_h;
     } else {
         tgx = m.gtx;
         tgy = m.gty;
     }
-    const real Fhat = -rcp * (ux * tgx + uy * tgy);
+    q.Fhat = -rcp * (ux * tgx + uy * tgy);
+    q.uu = ux * ux + uy * uy;
+    q.p3 = real(3) * m.p;
+    return q;
+}
 
-    const real uu = ux * ux + uy * uy;
-    const real p3 = real(3) * m.p;
-    const real theta = m.theta;
+// Post-collision values of direction k of one node (Eq. 14, the NS LBE and the
+// collision part of Eq. 28).  Directions 1..8 come first and accumulate their
+// changes in df, dh; the rest populations (k = 0) then take the balance:
+// f*_0 = f_0 + sum_{i>0} (f_i - f*_i), h*_0 = h_0 + Fhat + sum_{i>0} (h_i - h*_i),
+// equal to their BGK values in real arithmetic (sum_i f*_i = sum_i f_i,
+// sum_i h*_i = sum_i h_i + Fhat); this keeps the stored update mass- and
+// heat-neutral up to one rounding.  Otherwise each node relaxes toward w_i
+// times its rounded moment, and identical bulk nodes round alike, so FP32
+// storage drifts linearly in time.
+template <typename real, bool TRT>
+__device__ __forceinline__ void collide_dir(const Inst<real>& I, const Macro<real>& m, const Pre<real>& q, int k,
+                                            const real (&f)[9], const real (&g)[9], const real (&h)[9], real& df,
+                                            real& dh, real& fsk, real& gsk, real& hsk)
+{
+    const real w = wgt<real>(k);
+    const real cu = real(cx(k)) * m.ux + real(cy(k)) * m.uy;
+    // NS LBE: g^eq = 3 p (w_i - delta_i0) + rho s_i(u); G_i = w_i [3 c_i.F + 3 (c_i.u)(c_i.grad rho)]
+    const real si = w * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * q.uu);
+    const real geq = (k == 0 ? q.p3 * (w - real(1)) : q.p3 * w) + m.rho * si;
+    const real cF = real(cx(k)) * m.Fx + real(cy(k)) * m.Fy;
+    const real cg = real(cx(k)) * m.grx + real(cy(k)) * m.gry;
+    const real Gi = w * real(3) * (cF + cu * cg);
+    if (!TRT) {
+        gsk = g[k] - (g[k] - geq) * q.inv_tau_g + q.fac_g * Gi;
+    } else {
+        // even and odd parts under c_i -> -c_i of g_i, g_i^eq and G_i
+        const int kb = opp(k);
+        const real gp = real(0.5) * (g[k] + g[kb]), gm = real(0.5) * (g[k] - g[kb]);
+        const real ep = (k == 0 ? q.p3 * (w - real(1)) : q.p3 * w) + m.rho * w * (real(4.5) * cu * cu - real(1.5) * q.uu);
+        const real em = m.rho * w * real(3) * cu;
+        const real Gp = w * real(3) * (cu * cg), Gm = w * real(3) * cF;
+        gsk = g[k] - (gp - ep) * q.inv_tau_g - (gm - em) * q.inv_tau_gm + q.fac_g * Gp + q.fac_gm * Gm;
+    }
+    if (k == 0) {
+        fsk = f[0] + df;
+        hsk = (h[0] + q.Fhat) + dh;
+    } else {
+        // Eq. 14: f* = f - (f - f^eq)/tau_phi + (1 - 1/(2 tau_phi)) R_i
+        const real feq = w * (m.dphi + real(3) * m.phi * cu);
+        const real Ri = w * (real(cx(k)) * q.ax + real(cy(k)) * q.ay);
+        fsk = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
+        // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat; with two
+        // relaxation times the odd part (conduction) keeps tau_h
+        if (!TRT) {
+            hsk = h[k] - (h[k] - w * m.theta) * q.inv_tau_h + w * q.Fhat;
+        } else {
+            const int kb = opp(k);
+            const real hp = real(0.5) * (h[k] + h[kb]), hm = real(0.5) * (h[k] - h[kb]);
+            hsk = h[k] - (hp - w * m.theta) * q.inv_tau_hp - hm * q.inv_tau_h + w * q.Fhat;
+        }
+        df += f[k] - fsk;
+        dh += h[k] - hsk;
+    }
+}
 
-    // Collision (Eq. 14, the NS LBE, Eq. 28) and push streaming, one direction
-    // at a time so that each post-collision value is stored as soon as it
-    // exists.  The thermal update at the destination y = x + c_i is
-    // h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y).
-    // The rest populations come last and take the balance:
-    // f*_0 = f_0 + sum_{i>0} (f_i - f*_i), h*_0 = h_0 + Fhat + sum_{i>0} (h_i - h*_i),
-    // equal to their BGK values in real arithmetic (sum_i f*_i = sum_i f_i,
-    // sum_i h*_i = sum_i h_i + Fhat); this keeps the stored update mass- and
-    // heat-neutral up to one rounding.  Otherwise each node relaxes toward w_i
-    // times its rounded moment, and identical bulk nodes round alike, so FP32
-    // storage drifts linearly in time.
+// Collision and push streaming of the node (gi, gj) at patch entry c, whose
+// populations are f, g, h.  The thermal update at the destination y = x + c_i
+// is h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y).
+// Each direction is stored as soon as it is collided.
+template <typename real, int TX, int TY, bool EDGE, bool TRT>
+__device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<real, TX, TY>& S, int gi, int gj, int c,
+                                            int dst, const real (&f)[9], const real (&g)[9], const real (&h)[9])
+{
+    constexpr int PX = Patch<real, TX, TY>::PX;
+    const unsigned own = (unsigned)(gj * I.pitch + gi);
+    const gptr<real> Jx = to_global(I.jbase[0]), Jy = to_global(I.jbase[1]);
+    const real jpx = ld(Jx, own * (unsigned)sizeof(real)), jpy = ld(Jy, own * (unsigned)sizeof(real));
+    // destination rows and columns of the interior path (periodic wrap only)
+    unsigned drow[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
+    if (!EDGE) {
+        drow[0] = (unsigned)(wrap1(gj - 1, I.ny) * I.pitch);
+        drow[1] = (unsigned)(gj * I.pitch);
+        drow[2] = (unsigned)(wrap1(gj + 1, I.ny) * I.pitch);
+        dcol[0] = (unsigned)wrap1(gi - 1, I.nx);
+        dcol[1] = (unsigned)gi;
+        dcol[2] = (unsigned)wrap1(gi + 1, I.nx);
+    }
+
+    const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
+    real jx, jy;
+    const Pre<real> q = pre_collide<real, TRT>(I, m, f, h, jpx, jpy, jx, jy);
+    st(Jx, own * (unsigned)sizeof(real), jx);
+    st(Jy, own * (unsigned)sizeof(real), jy);
+
     real df = 0, dh = 0;
 #pragma unroll
     for (int kk = 1; kk <= 9; ++kk) {
         const int k = kk % 9;  // directions 1..8, then the rest population
-        const real w = wgt<real>(k);
-        const real cu = real(cx(k)) * ux + real(cy(k)) * uy;
-        // NS LBE: g^eq = 3 p (w_i - delta_i0) + rho s_i(u); G_i = w_i [3 c_i.F + 3 (c_i.u)(c_i.grad rho)]
-        const real si = w * (real(3) * cu + real(4.5) * cu * cu - real(1.5) * uu);
-        const real geq = (k == 0 ? p3 * (w - real(1)) : p3 * w) + m.rho * si;
-        const real cF = real(cx(k)) * m.Fx + real(cy(k)) * m.Fy;
-        const real cg = real(cx(k)) * m.grx + real(cy(k)) * m.gry;
-        const real Gi = w * real(3) * (cF + cu * cg);
-        real gsk;
-        if (!TRT) {
-            gsk = g[k] - (g[k] - geq) * inv_tau_g + fac_g * Gi;
-        } else {
-            // even and odd parts under c_i -> -c_i of g_i, g_i^eq and G_i
-            const int kb = opp(k);
-            const real gp = real(0.5) * (g[k] + g[kb]), gm = real(0.5) * (g[k] - g[kb]);
-            const real ep = (k == 0 ? p3 * (w - real(1)) : p3 * w) + m.rho * w * (real(4.5) * cu * cu - real(1.5) * uu);
-            const real em = m.rho * w * real(3) * cu;
-            const real Gp = w * real(3) * (cu * cg), Gm = w * real(3) * cF;
-            gsk = g[k] - (gp - ep) * inv_tau_g - (gm - em) * inv_tau_gm + fac_g * Gp + fac_gm * Gm;
-        }
-        real fsk, hsk;
-        if (k == 0) {
-            fsk = f[0] + df;
-            hsk = (h[0] + Fhat) + dh;
-        } else {
-            // Eq. 14: f* = f - (f - f^eq)/tau_phi + (1 - 1/(2 tau_phi)) R_i
-            const real feq = w * (m.dphi + real(3) * phi * cu);
-            const real Ri = w * (real(cx(k)) * ax + real(cy(k)) * ay);
-            fsk = f[k] - (f[k] - feq) * I.inv_tau_phi + I.fac_phi * Ri;
-            // Eq. 28 collision part: h - (h - w_i T)/tau_h + w_i Fhat; with two
-            // relaxation times the odd part (conduction) keeps tau_h
-            if (!TRT) {
-                hsk = h[k] - (h[k] - w * theta) * inv_tau_h + w * Fhat;
-            } else {
-                const int kb = opp(k);
-                const real hp = real(0.5) * (h[k] + h[kb]), hm = real(0.5) * (h[k] - h[kb]);
-                hsk = h[k] - (hp - w * theta) * inv_tau_hp - hm * inv_tau_h + w * Fhat;
-            }
-            df += f[k] - fsk;
-            dh += h[k] - hsk;
-        }
+        real fsk, gsk, hsk;
+        collide_dir<real, TRT>(I, m, q, k, f, g, h, df, dh, fsk, gsk, hsk);
         unsigned di = 0;
         int side = 0;
         bool in_lattice = true;
@@ -487,13 +510,15 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
         else di = drow[cy(k) + 1] + dcol[cx(k) + 1];
         if (in_lattice) {
             const int cd = c + cy(k) * PX + cx(k);
-            st(plane_of(B, kF + k, P), di * (unsigned)sizeof(real), (real)(fsk));
-            st(plane_of(B, kG + k, P), di * (unsigned)sizeof(real), (real)(gsk));
+            st(dst_plane(I, dst, kF + k), di * (unsigned)sizeof(real), (real)(fsk));
+            st(dst_plane(I, dst, kG + k), di * (unsigned)sizeof(real), (real)(gsk));
             const real hold = S.h[k][cd];
-            st(plane_of(B, kH + k, P), di * (unsigned)sizeof(real), (real)(hold + (hsk - hold) * S.irc[cd]));
+            st(dst_plane(I, dst, kH + k), di * (unsigned)sizeof(real), (real)(hold + (hsk - hold) * S.irc[cd]));
         } else if (EDGE) {
             const int kb = opp(k);
             const int bc = I.bc[side];
+            const real w = wgt<real>(k);
+            const real cu = real(cx(k)) * m.ux + real(cy(k)) * m.uy;
             const real s = side < 2 ? real(gj) + real(0.5) * real(cy(k)) : real(gi) + real(0.5) * real(cx(k));
             real fb, gb, hb;
             if (bc == BC_WALL_T || bc == BC_WALL_ADIABATIC) {
@@ -513,15 +538,27 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
                 hb = -hsk + real(2) * w * I.T_in_d;
             } else {  // outlet: anti-bounce-back at p = 0 with the node's own u, phi, T
                 fb = -fsk + real(2) * w * m.dphi;
-                gb = -gsk + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * uu);
-                hb = -hsk + real(2) * w * theta;
+                gb = -gsk + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * q.uu);
+                hb = -hsk + real(2) * w * m.theta;
             }
-            st(plane_of(B, kF + kb, P), own * (unsigned)sizeof(real), (real)(fb));
-            st(plane_of(B, kG + kb, P), own * (unsigned)sizeof(real), (real)(gb));
+            st(dst_plane(I, dst, kF + kb), own * (unsigned)sizeof(real), (real)(fb));
+            st(dst_plane(I, dst, kG + kb), own * (unsigned)sizeof(real), (real)(gb));
             const real hold = S.h[kb][c];
-            st(plane_of(B, kH + kb, P), own * (unsigned)sizeof(real), (real)(hold + (hb - hold) * S.irc[c]));
+            st(dst_plane(I, dst, kH + kb), own * (unsigned)sizeof(real), (real)(hold + (hb - hold) * S.irc[c]));
         }
     }
+}
+
+// One node per work-item.
+template <typename real, int TX, int TY, bool EDGE, bool TRT>
+__device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
+{
+    real f[9], g[9], h[9];
+    const bool inside = load_patch<real, TX, TY, EDGE>(I, src, S, x0, y0, f, g, h);
+    if (!inside) return;
+    const int tid = threadIdx.x;
+    const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
+    node_update<real, TX, TY, EDGE, TRT>(I, S, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h);
 }
 
 // Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
@@ -536,6 +573,7 @@ __device__ inline void my_tiles(int ntiles, int& t0, int& t1)
     t1 = (int)((long long)(L + 1) * ntiles / G);
 }
 
+// One step of every tile in the table, one node per work-item.
 // ANY_TRT: some lattice of the launch uses two relaxation times (a separate
 // kernel, so that the BGK-only kernel keeps its own register budget).
 template <typename real, int TX, int TY, bool ANY_TRT>
@@ -579,8 +617,8 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h);
+                                ? load_patch<real, TX, TY, false>(I, src, S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, src, S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -725,8 +763,8 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, to_global<const real>(I.pop[src]), S, tl.x0, tl.y0, f, g, h);
+                                ? load_patch<real, TX, TY, false>(I, src, S, tl.x0, tl.y0, f, g, h)
+                                : load_patch<real, TX, TY, true>(I, src, S, tl.x0, tl.y0, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -868,6 +906,7 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     return hipGetLastError();
 }
 
+// Tile id -> (TX, TY), in the order of kTileTX and kTileTY.
 #define LBM_TILE_SWITCH(TILE, CALL)                  \
     switch (TILE) {                                  \
     case 0: return CALL(64, 4);                      \

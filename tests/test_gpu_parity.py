@@ -121,6 +121,27 @@ def test_tile_shapes_bitwise():
                 assert np.array_equal(st[k], ref[k]), f"tile {t}: {k} differs"
 
 
+@pytest.mark.parametrize("prec", ["FP64", "FP32_DEV"])
+def test_tile_shapes_bitwise_periodic_x(prec):
+    """Interior tiles (periodic wrap at both ends of a tile row, walls in y)
+    give bitwise the same state for every tile shape.  nx = 320: whole and
+    partial tiles in each row for the 64-, 128- and 256-wide shapes."""
+    cfg, f0 = wl.tiny(320, 40, bc=wl.ALL_BCS[1], seed=6)
+    announce("tile_shapes_bitwise_periodic_x", prec)
+    ref = None
+    for t in range(len(lbm.tile_shapes())):
+        lat = lbm.Lattice(cfg, f0, getattr(lbm, prec))
+        lat.set_tile(t)
+        lat.step(21)
+        st = lat.get_state()
+        lat.close()
+        if ref is None:
+            ref = st
+        else:
+            for k in ("f", "g", "h", "jprev"):
+                assert np.array_equal(st[k], ref[k]), f"tile {t}: {k} differs"
+
+
 def test_graph_capture_bitwise():
     cfg, f0 = wl.tiny(64, 40, seed=4)
     announce("graph_capture_bitwise")
