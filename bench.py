@@ -106,8 +106,9 @@ def time_gpu(items, prec, steps, warmup, tile=None, autotune=False):
     ms = ev0.elapsed_time(ev1)
     d = lat.diagnostics()
     nodes = sum(c["nx"] * c["ny"] for c, _ in items)
+    tile_used = "x".join(str(v) for v in lbm.tile_shapes()[lat.tile()])
     lat.close()
-    return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes, tuned=tuned,
+    return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes, tuned=tuned, tile=tile_used,
                 mlups=nodes * steps / (ms * 1e-3) / 1e6, finite=d["n_nonfinite"] == 0, max_u=d["max_u"])
 
 
@@ -235,7 +236,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu"),
+        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu", tile=r32["tile"]),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }
@@ -255,6 +256,7 @@ def main():
         b64 = lbm.bytes_per_update(lbm.FP64) * r64["nodes"]
         a64 = b64 / (r64["ms_per_step"] * 1e-3) / 1e9
         out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
+                       "tile": r64["tile"],
                        "working_set_bytes": (2 * 27 + 2) * 8 * r64["nodes"],
                        "roofline": {"bound": "hbm", "achieved": round(a64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(a64 / HBM_PEAK_GBS, 4),
