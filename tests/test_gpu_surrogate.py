@@ -36,6 +36,16 @@ def host(t):
     return t.float().cpu().numpy().astype(np.float64)
 
 
+def dev(stream, *tensors):
+    """Orders work on `stream` after the creation of the given device tensors
+    (made on torch's current stream).  The caller keeps the returned tensors
+    referenced until `stream` is synchronized: the caching allocator would
+    otherwise hand their memory to the next allocation while a kernel on
+    `stream` still reads it."""
+    stream.wait_stream(torch.cuda.current_stream())
+    return tensors
+
+
 def relmax(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
@@ -57,7 +67,8 @@ def test_conv_forward(cin, relu_in, dil, stream):
     b = rng.standard_normal(32).astype(np.float32)
     res = rng.standard_normal((N, H, W, 32)).astype(np.float32)
     out = torch.empty((N, H, W, 32), device="cuda")
-    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), t_f32(res), None, out, relu_in, stream, dil)
+    xd, wd, bd, rd = dev(stream, t_bf16(x), t_bf16(w), t_f32(b), t_f32(res))
+    sur.sur_conv3x3(xd, cin, wd, bd, rd, None, out, relu_in, stream, dil)
     stream.synchronize()
     a = cr.relu(x) if relu_in else x
     ref = cr.conv(a, w, b, dil) + res
@@ -65,7 +76,8 @@ def test_conv_forward(cin, relu_in, dil, stream):
     # BF16 output with a mask
     mask = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
     outb = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
-    sur.sur_conv3x3(t_bf16(x), cin, t_bf16(w), t_f32(b), None, t_bf16(mask), outb, relu_in, stream, dil)
+    (md,) = dev(stream, t_bf16(mask))
+    sur.sur_conv3x3(xd, cin, wd, bd, None, md, outb, relu_in, stream, dil)
     stream.synchronize()
     refb = cr.bf16_round(cr.conv(a, w, b, dil) * (mask > 0))
     got = host(outb)
@@ -80,9 +92,10 @@ def test_adjoint_input_gradient(stream):
         w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
         g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
         wt = torch.empty((32, 9, 32), dtype=torch.bfloat16, device="cuda")
-        sur.sur_adjoint_weights(t_bf16(w), cin, wt, stream)
+        wd, gd = dev(stream, t_bf16(w), t_bf16(g))
+        sur.sur_adjoint_weights(wd, cin, wt, stream)
         out = torch.empty((N, H, W, 32), device="cuda")
-        sur.sur_conv3x3(t_bf16(g), 32, wt, None, None, None, out, False, stream, dil)
+        sur.sur_conv3x3(gd, 32, wt, None, None, None, out, False, stream, dil)
         stream.synchronize()
         ref = cr.conv_input_grad(g, w, dil)
         got = host(out)[..., :cin]
@@ -103,13 +116,15 @@ def test_weight_and_bias_gradient(cin, dil, stream):
         groups = 13
         part = torch.empty(groups * 32 * 9 * cin, device="cuda")
         out = torch.empty((32, 9, cin), device="cuda")
-        sur.sur_weight_grad(t_bf16(g), t_bf16(a), cin, relu_in, part, groups, out, stream, dil)
+        gd, ad = dev(stream, t_bf16(g), t_bf16(a))
+        sur.sur_weight_grad(gd, ad, cin, relu_in, part, groups, out, stream, dil)
         stream.synchronize()
         ref = cr.conv_weight_grad(g, cr.relu(a) if relu_in else a, dil)
         assert relmax(host(out), ref) <= 2e-5
     bpart = torch.empty(5 * 32, device="cuda")
     bout = torch.empty(32, device="cuda")
-    sur.sur_bias_grad(t_bf16(g), bpart, 5, bout, stream)
+    (gd,) = dev(stream, t_bf16(g))
+    sur.sur_bias_grad(gd, bpart, 5, bout, stream)
     stream.synchronize()
     assert relmax(host(bout), g.sum(axis=(0, 1, 2))) <= 2e-5
 
@@ -123,6 +138,7 @@ def test_adam_and_mse(stream):
     m2 = np.zeros(1000)
     tp, tg, tm1, tm2 = t_f32(p), t_f32(gr), t_f32(m1), t_f32(m2)
     pb = torch.empty(1000, dtype=torch.bfloat16, device="cuda")
+    dev(stream, tp, tg, tm1, tm2, pb)
     for t in (1, 2, 3):
         sur.sur_adam(tp, tg, tm1, tm2, pb, 1e-2, t, stream)
         p, m1, m2 = cr.adam(p, gr, m1, m2, t, lr=1e-2)
@@ -134,7 +150,8 @@ def test_adam_and_mse(stream):
     tg4 = rng.standard_normal((N, H, W, 4)).astype(np.float32)
     grad = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
     part = torch.empty(7, device="cuda")
-    sur.sur_mse(t_f32(d), t_f32(tg4), 0.25, grad, part, stream)
+    dd, td = dev(stream, t_f32(d), t_f32(tg4))
+    sur.sur_mse(dd, td, 0.25, grad, part, stream)
     stream.synchronize()
     e = d[..., :4].astype(np.float64) - tg4
     assert abs(float(part.sum()) - np.sum(e * e)) <= 1e-5 * np.sum(e * e)
@@ -209,6 +226,7 @@ def test_pack_target_and_advance(stream):
     h, w = 9, 64
     f0, f1 = _rand_state(rng, h, w), _rand_state(rng, h, w)
     x = torch.empty((h, w, 8), dtype=torch.bfloat16, device="cuda")
+    dev(stream)
     sur.sur_pack(f0, sc, x, stream)
     t = torch.empty((h, w, 5), device="cuda")
     sur.sur_pack_target(f0, f1, sc, t, stream)
@@ -249,6 +267,7 @@ def test_light_volume_and_judge(stream):
     a, b = _rand_state(rng, h, w), _rand_state(rng, h, w)
     part = torch.empty(8 * 13, dtype=torch.float64, device="cuda")
     out = torch.full((8,), -7.0, dtype=torch.float64, device="cuda")
+    dev(stream)
     sur.sur_light_volume(a["phi"], part, out[:1], stream)
     stream.synchronize()
     phi = a["phi"].double().cpu().numpy()
