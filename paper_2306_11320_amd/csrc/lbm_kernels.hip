@@ -198,7 +198,7 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int gi = x0 + lx, gj = y0 + ly;
-    const bool inside = gi < I.nx && gj < I.ny;
+    const bool inside = !EDGE || (gi < I.nx && gj < I.ny);  // interior tiles are whole
     const int c = (ly + 1) * PT::PX + (lx + 1);
     if (inside) {
         const unsigned idx = (unsigned)(gj * I.pitch + gi);
@@ -584,7 +584,12 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
     int t0, t1;
     my_tiles(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
-        const Tile tl = tiles[t];
+        // the tile entry is the same for the whole workgroup: keep it scalar
+        Tile tl = tiles[t];
+        tl.inst = __builtin_amdgcn_readfirstlane(tl.inst);
+        tl.x0 = __builtin_amdgcn_readfirstlane(tl.x0);
+        tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
+        tl.flags = __builtin_amdgcn_readfirstlane(tl.flags);
         const Inst<real>& I = insts[tl.inst];
         const bool interior = tl.flags & kTileInterior;
         if (!ANY_TRT || I.collision == 0) {

@@ -19,6 +19,7 @@ ABI_VERSION = 2
 
 LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_DEV = 0, 1
+BGK, TRT = 0, 1
 OUT_F64, OUT_F32 = 0, 1
 
 EXPORTED = [

@@ -115,6 +115,28 @@ def test_batch_equals_single_bitwise(prec):
         assert np.array_equal(fa["p"], fb["p"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mixed_collision_batch_bitwise(prec):
+    """A batch of BGK and TRT lattices runs the TRT-capable kernel, whose BGK
+    branch must give the BGK lattices bitwise what a BGK-only launch gives, and
+    its TRT lattices what they get alone."""
+    P = lbm.FP64 if prec == "fp64" else lbm.FP32_DEV
+    items = [wl.tiny(70, 33, bc=wl.ALL_BCS[1], seed=1), wl.tiny(131, 64, bc=wl.ALL_BCS[4], seed=2),
+             wl.tiny(96, 40, bc=wl.ALL_BCS[2], seed=3)]
+    items[1][0]["collision"] = lbm.TRT
+    announce("mixed_collision_batch", prec)
+    batch = lbm.Lattice.batch(items, P)
+    batch.step(29)
+    for k, (cfg, f0) in enumerate(items):
+        single = lbm.Lattice(cfg, f0, P)
+        single.step(29)
+        sa, sb = batch.get_state(k), single.get_state()
+        for fam in ("f", "g", "h", "jprev"):
+            assert np.array_equal(sa[fam], sb[fam]), (k, fam)
+        single.close()
+    batch.close()
+
+
 def test_batch_persistent_grid_sizes():
     """The persistent grid may be any size: results do not depend on it."""
     items = [wl.tiny(100, 40, seed=1), wl.tiny(64, 90, bc=wl.ALL_BCS[4], seed=2)]
