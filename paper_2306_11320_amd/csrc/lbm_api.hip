@@ -341,9 +341,12 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
             for (int y = 0; y < ny; y += ty)
                 for (int x = 0; x < nx; x += tx) {
                     const bool whole = x + tx <= nx && y + ty <= ny;
-                    const bool inx = px ? nx >= 3 : (x >= 1 && x + tx <= nx - 1);
-                    const bool iny = py ? ny >= 3 : (y >= 1 && y + ty <= ny - 1);
-                    tl.push_back(lbm::Tile{k, x, y, (whole && inx && iny) ? lbm::kTileInterior : 0});
+                    // wrap-only: in a periodic direction one wrap must reach
+                    // every point of the tile and its ring (tile no longer
+                    // than the lattice)
+                    const bool inx = px ? (nx >= 3 && tx <= nx) : (x >= 1 && x + tx <= nx - 1);
+                    const bool iny = py ? (ny >= 3 && ty <= ny) : (y >= 1 && y + ty <= ny - 1);
+                    tl.push_back(lbm::Tile{k, x, y, (inx && iny ? lbm::kTileInterior : 0) | (whole ? lbm::kTileWhole : 0)});
                 }
         }
         c->d_tiles[t] = reinterpret_cast<lbm::Tile*>(c->ws + off_tiles[t]);

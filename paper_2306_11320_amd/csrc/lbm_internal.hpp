@@ -44,9 +44,11 @@ struct Inst {
 struct Tile {
     int inst, x0, y0, flags;
 };
-// The tile is whole and neither it nor its one-node ring crosses a wall, inlet
-// or outlet: streaming and ring loads need at most a periodic wrap.
+// Neither the tile nor its one-node ring crosses a wall, inlet or outlet:
+// streaming and ring loads need at most one periodic wrap.
 constexpr int kTileInterior = 1;
+// The tile lies inside the lattice (else its last columns or rows do not).
+constexpr int kTileWhole = 2;
 
 // Sums accumulated by the FP64 diagnostics reduction, per lattice.
 enum DiagSlot {

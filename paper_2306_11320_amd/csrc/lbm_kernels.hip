@@ -190,7 +190,7 @@ __device__ inline void fill_entry(const Inst<real>& I, int src, Patch<real, TX, 
 
 // Loads the work-item's own node and fills the patch.  Returns whether the
 // work-item's node lies in the lattice.
-template <typename real, int TX, int TY, bool EDGE>
+template <typename real, int TX, int TY, bool EDGE, bool WHOLE>
 __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int x0,
                                   int y0, real (&f)[9], real (&g)[9], real (&h)[9])
 {
@@ -198,7 +198,7 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int gi = x0 + lx, gj = y0 + ly;
-    const bool inside = !EDGE || (gi < I.nx && gj < I.ny);  // interior tiles are whole
+    const bool inside = WHOLE || (gi < I.nx && gj < I.ny);
     const int c = (ly + 1) * PT::PX + (lx + 1);
     if (inside) {
         const unsigned idx = (unsigned)(gj * I.pitch + gi);
@@ -550,15 +550,40 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
 }
 
 // One node per work-item.
-template <typename real, int TX, int TY, bool EDGE, bool TRT>
+template <typename real, int TX, int TY, bool EDGE, bool WHOLE, bool TRT>
 __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
 {
     real f[9], g[9], h[9];
-    const bool inside = load_patch<real, TX, TY, EDGE>(I, src, S, x0, y0, f, g, h);
+    const bool inside = load_patch<real, TX, TY, EDGE, WHOLE>(I, src, S, x0, y0, f, g, h);
     if (!inside) return;
     const int tid = threadIdx.x;
     const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
     node_update<real, TX, TY, EDGE, TRT>(I, S, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h);
+}
+
+// Interior tiles take the wrap-only path; a whole one needs no per-node
+// inside test (a partial one, cut by the lattice's end in a periodic
+// direction, does).
+template <typename real, int TX, int TY, bool TRT>
+__device__ __forceinline__ void tile_any(const Inst<real>& I, const Tile& tl, int src, Patch<real, TX, TY>& S)
+{
+    if (tl.flags & kTileInterior) {
+        if (tl.flags & kTileWhole) tile_step<real, TX, TY, false, true, TRT>(I, tl.x0, tl.y0, src, S);
+        else tile_step<real, TX, TY, false, false, TRT>(I, tl.x0, tl.y0, src, S);
+    } else {
+        tile_step<real, TX, TY, true, false, TRT>(I, tl.x0, tl.y0, src, S);
+    }
+}
+
+template <typename real, int TX, int TY>
+__device__ __forceinline__ bool load_any(const Inst<real>& I, const Tile& tl, int src, Patch<real, TX, TY>& S,
+                                         real (&f)[9], real (&g)[9], real (&h)[9])
+{
+    if (tl.flags & kTileInterior) {
+        if (tl.flags & kTileWhole) return load_patch<real, TX, TY, false, true>(I, src, S, tl.x0, tl.y0, f, g, h);
+        return load_patch<real, TX, TY, false, false>(I, src, S, tl.x0, tl.y0, f, g, h);
+    }
+    return load_patch<real, TX, TY, true, false>(I, src, S, tl.x0, tl.y0, f, g, h);
 }
 
 // Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
@@ -591,14 +616,8 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
         tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
         tl.flags = __builtin_amdgcn_readfirstlane(tl.flags);
         const Inst<real>& I = insts[tl.inst];
-        const bool interior = tl.flags & kTileInterior;
-        if (!ANY_TRT || I.collision == 0) {
-            if (interior) tile_step<real, TX, TY, false, false>(I, tl.x0, tl.y0, src, S);
-            else tile_step<real, TX, TY, true, false>(I, tl.x0, tl.y0, src, S);
-        } else {
-            if (interior) tile_step<real, TX, TY, false, true>(I, tl.x0, tl.y0, src, S);
-            else tile_step<real, TX, TY, true, true>(I, tl.x0, tl.y0, src, S);
-        }
+        if (!ANY_TRT || I.collision == 0) tile_any<real, TX, TY, false>(I, tl, src, S);
+        else tile_any<real, TX, TY, true>(I, tl, src, S);
         if (t + 1 < t1) __syncthreads();
     }
 }
@@ -621,9 +640,7 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         const Tile tl = tiles[t];
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
-        const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, src, S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, src, S, tl.x0, tl.y0, f, g, h);
+        const bool inside = load_any(I, tl, src, S, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
@@ -767,9 +784,7 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         const Tile tl = tiles[t];
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
-        const bool inside = (tl.flags & kTileInterior)
-                                ? load_patch<real, TX, TY, false>(I, src, S, tl.x0, tl.y0, f, g, h)
-                                : load_patch<real, TX, TY, true>(I, src, S, tl.x0, tl.y0, f, g, h);
+        const bool inside = load_any(I, tl, src, S, f, g, h);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;

@@ -122,12 +122,14 @@ def test_tile_shapes_bitwise():
 
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32_DEV"])
-def test_tile_shapes_bitwise_periodic_x(prec):
-    """Interior tiles (periodic wrap at both ends of a tile row, walls in y)
-    give bitwise the same state for every tile shape.  nx = 320: whole and
-    partial tiles in each row for the 64-, 128- and 256-wide shapes."""
-    cfg, f0 = wl.tiny(320, 40, bc=wl.ALL_BCS[1], seed=6)
-    announce("tile_shapes_bitwise_periodic_x", prec)
+@pytest.mark.parametrize("bcs,ny", [(wl.ALL_BCS[1], 40), (wl.ALL_BCS[0], 42)])
+def test_tile_shapes_bitwise_periodic_x(prec, bcs, ny):
+    """Interior tiles (periodic wrap at both ends of a tile row) give bitwise
+    the same state for every tile shape.  nx = 320: whole tiles and tiles cut
+    by the lattice's end in x (interior when x is periodic); with ny = 42 and
+    y periodic, also tiles cut in y."""
+    cfg, f0 = wl.tiny(320, ny, bc=bcs, seed=6)
+    announce("tile_shapes_bitwise_periodic_x", prec, bcs, ny)
     ref = None
     for t in range(len(lbm.tile_shapes())):
         lat = lbm.Lattice(cfg, f0, getattr(lbm, prec))
