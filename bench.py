@@ -197,8 +197,8 @@ def main():
                     help="only run the plain copy kernel on MIB MiB, 20 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the lattice update is not sharded "
-              "across GPUs in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the lattice update runs on one GPU "
+              "and is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2306_11320_amd import lbm
