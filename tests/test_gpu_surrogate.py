@@ -57,11 +57,13 @@ def stream():
 
 @pytest.mark.parametrize("cin", [8, 32])
 @pytest.mark.parametrize("relu_in", [False, True])
-@pytest.mark.parametrize("dil", [1, 3])
-def test_conv_forward(cin, relu_in, dil, stream):
-    rng = np.random.default_rng(cin + relu_in + 10 * dil)
-    N, H, W = 2, 5, 64
-    announce("conv_forward", cin, relu_in, dil)
+@pytest.mark.parametrize("dil,W", [(1, 64), (3, 64), (1, 256), (3, 256), (16, 256), (2, 128)])
+def test_conv_forward(cin, relu_in, dil, W, stream):
+    """Frame widths of one to eight 32-pixel segments per row (periodic wrap at
+    both ends of the row) and dilations up to 16."""
+    rng = np.random.default_rng(cin + relu_in + 10 * dil + W)
+    N, H = 2, 5
+    announce("conv_forward", cin, relu_in, dil, W)
     x = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
     w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
     b = rng.standard_normal(32).astype(np.float32)
@@ -86,9 +88,9 @@ def test_conv_forward(cin, relu_in, dil, stream):
 
 def test_adjoint_input_gradient(stream):
     rng = np.random.default_rng(7)
-    N, H, W = 1, 6, 32
+    N, H = 1, 6
     announce("adjoint")
-    for cin, dil in ((8, 1), (32, 1), (32, 2), (8, 5)):
+    for cin, dil, W in ((8, 1, 32), (32, 1, 32), (32, 2, 32), (8, 5, 32), (32, 4, 128), (8, 16, 256)):
         w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
         g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
         wt = torch.empty((32, 9, 32), dtype=torch.bfloat16, device="cuda")
