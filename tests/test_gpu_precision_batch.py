@@ -48,6 +48,22 @@ def test_fp32_dev_vs_oracle(bcs):
         check_fp32(lat.fields(), o.fields(), cfg["T_ref"])
 
 
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[1], wl.ALL_BCS[4]], ids=["channel", "inlet"])
+def test_fp32_dev_trt_vs_oracle(bcs):
+    """FP32 deviation storage with the two-relaxation-time collision, against
+    the FP64 oracle's TRT step, to the same tolerances as BGK."""
+    cfg, f0 = wl.tiny(96, 72, bc=bcs, seed=8)
+    cfg.update(collision=lbm.TRT, trt_magic=3.0 / 16.0)
+    announce("fp32_dev_trt_vs_oracle", bcs)
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    for _ in range(2):
+        o.step(500)
+        lat.step(500)
+        check_fp32(lat.fields(), o.fields(), cfg["T_ref"])
+    lat.close()
+
+
 def test_fp32_dev_full_droplet():
     """The benchmark workload (256 x 1024 droplet, Ma = 1, ratio 0.5), 600 steps."""
     cfg, f0 = wl.droplet(Ma=1.0, ratio=0.5)
