@@ -10,7 +10,9 @@
 //   2. isotropic stencils for grad phi, lap phi, grad T from LDS; properties,
 //      sigma(T), the interfacial force of Eq. 11, u and p (Sec. 3.1), the time
 //      derivative of phi u (Sec. 4 preamble);
-//   3. the three BGK collisions (Eq. 14, the NS LBE, Eq. 28);
+//   3. the three collisions (Eq. 14, the NS LBE, Eq. 28): BGK, or two
+//      relaxation times for the NS and thermal LBEs (a separate kernel, used
+//      when some lattice of the launch asks for it);
 //   4. push streaming to the other time level with the boundary rules folded
 //      in; the thermal update divides by the destination's heat capacitance
 //      and blends with the destination's old h_i, both read from LDS.
@@ -18,7 +20,8 @@
 //
 // Storage is structure-of-arrays planes, x fastest, f and h kept as deviations
 // from w_i phi0 and w_i T0 (exact for BGK, streaming, bounce-back and the
-// blend, whose weights sum to one), g as is.
+// blend, whose weights sum to one), g as is.  The bases of the 27 planes of
+// each time level come precomputed in the lattice's parameter block.
 #include "lbm_internal.hpp"
 
 namespace lbm {
