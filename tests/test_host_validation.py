@@ -1,0 +1,66 @@
+"""Host-side parameter validation of the C ABI (no GPU call is made):
+lbm_workspace_bytes returns 0 and lbm_last_error names the cause for every
+parameter set the library rejects, and the workspace size of a valid lattice
+holds the two time levels of 27 population planes."""
+import ctypes as C
+
+import pytest
+
+from paper_2306_11320_amd import workloads as wl
+
+lbm = pytest.importorskip("paper_2306_11320_amd.lbm")
+
+
+def _lib():
+    try:
+        return lbm.lib()
+    except RuntimeError as e:
+        pytest.fail(str(e))
+
+
+def _params(**over):
+    cfg, _ = wl.tiny(40, 24, bc=wl.ALL_BCS[1], seed=1)
+    p = lbm.make_params(cfg, lbm.FP32_DEV)
+    for k, v in over.items():
+        if k == "bc":
+            for s in range(4):
+                p.bc[s] = v[s]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def test_valid_lattice_workspace():
+    L = _lib()
+    p = _params()
+    n = L.lbm_workspace_bytes(C.byref(p))
+    pitch = 64  # 40 rounded up to 32
+    plane = pitch * 24
+    assert n >= 2 * 27 * plane * 4 + 2 * plane * 4
+    p64 = _params(precision=lbm.FP64)
+    assert L.lbm_workspace_bytes(C.byref(p64)) >= 2 * 27 * plane * 8
+
+
+@pytest.mark.parametrize("over,why", [
+    (dict(abi_version=lbm.ABI_VERSION + 1), "abi_version"),
+    (dict(nx=2), "smaller than 3x3"),
+    (dict(nx=20000, ny=20000), "too large"),
+    (dict(precision=7), "precision"),
+    (dict(bc=[wl.PERIODIC, wl.WALL_T, wl.WALL_T, wl.WALL_T]), "periodic paired"),
+    (dict(grad_mode=2), "grad_mode"),
+    (dict(collision=2), "collision"),
+    (dict(reserved=1), "reserved"),
+    (dict(collision=lbm.TRT, trt_magic=0.0), "trt_magic"),
+    (dict(n_bubbles=5), "tracked regions"),
+    (dict(rho_l=0.0), "densities"),
+    (dict(mu_h=-1.0), "viscosities"),
+    (dict(lambda_l=0.0), "conductivities"),
+    (dict(rhocp_h=0.0), "heat capacitances"),
+    (dict(mobility=0.0), "mobility"),
+    (dict(W=0.0), "interface width"),
+])
+def test_rejected_parameters(over, why):
+    L = _lib()
+    p = _params(**over)
+    assert L.lbm_workspace_bytes(C.byref(p)) == 0
+    assert why in L.lbm_last_error().decode()
