@@ -41,7 +41,7 @@ def build() -> str:
 class Params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4), ("grad_mode", C.c_int32),
-        ("n_bubbles", C.c_int32), ("collision", C.c_int32), ("pad_", C.c_int32), ("trt_magic", C.c_double),
+        ("n_bubbles", C.c_int32), ("collision", C.c_int32), ("force_form", C.c_int32), ("trt_magic", C.c_double),
         ("rho_l", C.c_double), ("rho_h", C.c_double), ("mu_l", C.c_double), ("mu_h", C.c_double),
         ("lam_l", C.c_double), ("lam_h", C.c_double), ("rcp_l", C.c_double), ("rcp_h", C.c_double),
         ("sigma_ref", C.c_double), ("sigma_T", C.c_double), ("sigma_TT", C.c_double), ("T_ref", C.c_double),
@@ -112,6 +112,7 @@ def make_params(cfg: dict) -> Params:
         p.tw_slope[s] = float(cfg.get("tw_slope", [0.0] * 4)[s])
     p.grad_mode = int(cfg.get("grad_mode", 0))
     p.collision = int(cfg.get("collision", 0))
+    p.force_form = int(cfg.get("force_form", 0))
     p.trt_magic = float(cfg.get("trt_magic", 0.1875))
     bx = list(cfg.get("bubbles_x", []))
     by = list(cfg.get("bubbles_y", []))

@@ -36,6 +36,10 @@
  *     the viscosity of the NS LBE, odd for the conductivity of the thermal LBE),
  *     the other one follows from (tau+ - 1/2)(tau- - 1/2) = trt_magic; each
  *     part of the forcing term gets its own factor 1 - 1/(2 tau);
+ *   - interfacial force (force_form = 1): the capillary term of Eq. 11 in the
+ *     potential form -phi grad mu_phi (not in the paper; equal to mu_phi grad phi
+ *     up to a gradient), mu_phi on the first ghost ring from phi extended to a
+ *     second ring by the same ghost rules, grad mu_phi by the isotropic stencil;
  *   - halfway bounce-back walls, anti-bounce-back Dirichlet temperature walls,
  *     bounce-back adiabatic walls; inlet: anti-bounce-back for phi and T and
  *     moving-wall bounce-back for the inflow velocity; outlet: anti-bounce-back
@@ -68,7 +72,8 @@ typedef struct {
     int32_t grad_mode;  /* 0: normal and grad T from moments; 1: from the stencils */
     int32_t n_bubbles;  /* number of tracked light-phase regions (<= 4) */
     int32_t collision;  /* 0: BGK; 1: two-relaxation-time for the NS and thermal LBEs */
-    int32_t pad_;
+    int32_t force_form; /* 0: capillary term (sigma/W^2) mu_phi grad phi, final form of Eq. 11;
+                           1: potential form -(sigma/W^2) phi grad mu_phi */
     double trt_magic;   /* (tau+ - 1/2)(tau- - 1/2) of the two-relaxation-time collision */
     double rho_l, rho_h, mu_l, mu_h, lam_l, lam_h, rcp_l, rcp_h;
     double sigma_ref, sigma_T, sigma_TT, T_ref;
@@ -106,6 +111,7 @@ typedef struct {
     double *dphx, *dphy, *lphi, *dTx, *dTy;
     double *jx, *jy;
     double *phipad, *Tpad; /* (nx+2)*(ny+2), ghost ring included */
+    double *mupad;         /* mu_phi on the same padded grid (potential form only) */
     double bx[4], by[4];    /* previous bubble centroids */
     int* writes;            /* when non-NULL: writes per slot of the new level, [3][9][n] */
 } orc_state;
@@ -219,6 +225,23 @@ static void macros(orc_state* S)
             S->Tpad[q] = field_at(S, S->T, KIND_T, i, j);
         }
 
+    /* potential form: mu_phi on the padded grid.  A ghost node takes the
+     * formula of Sec. 2 applied to the ghost values of phi, which extend to
+     * two nodes beyond the lattice by the same rules as the first ring. */
+    if (P->force_form == 1) {
+#pragma omp parallel for schedule(static)
+        for (int j = -1; j <= ny; ++j)
+            for (int i = -1; i <= nx; ++i) {
+                double pc = field_at(S, S->phi, KIND_PHI, i, j);
+                double lap = 0.0;
+                for (int k = 1; k < 9; ++k)
+                    lap += 2.0 * WI[k] * (field_at(S, S->phi, KIND_PHI, i + CX[k], j + CY[k]) - pc) / CS2;
+                const double phl = -1.0, phh = 1.0;
+                S->mupad[(size_t)(j + 1) * px + (i + 1)] =
+                    (pc - phl) * (pc - phh) * (pc - 0.5 * (phl + phh)) - P->W * P->W * lap;
+            }
+    }
+
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -258,12 +281,25 @@ static void macros(orc_state* S)
             double dsig = dsigma_dT(P, T);
             double gsx = dsig * gtx, gsy = dsig * gty;
 
-            /* interfacial force, final form of Eq. 11 */
+            /* interfacial force, final form of Eq. 11; the potential form
+             * replaces its capillary term mu_phi grad phi by -phi grad mu_phi
+             * (the two differ by the gradient of phi mu_phi) */
             double g2 = gpx * gpx + gpy * gpy;
             double sdotp = gsx * gpx + gsy * gpy;
             double pref = 3.0 * sqrt(2.0) * P->W / 4.0;
-            double Fx = pref * (g2 * gsx - sdotp * gpx + sig / (P->W * P->W) * mu_phi * gpx) + P->Gx;
-            double Fy = pref * (g2 * gsy - sdotp * gpy + sig / (P->W * P->W) * mu_phi * gpy) + P->Gy;
+            double capx = mu_phi * gpx, capy = mu_phi * gpy;
+            if (P->force_form == 1) {
+                double gmx = 0.0, gmy = 0.0;
+                for (int k = 0; k < 9; ++k) {
+                    double mn = S->mupad[(size_t)(j + 1 + CY[k]) * px + (i + 1 + CX[k])];
+                    gmx += WI[k] * CX[k] * mn / CS2;
+                    gmy += WI[k] * CY[k] * mn / CS2;
+                }
+                capx = -phi * gmx;
+                capy = -phi * gmy;
+            }
+            double Fx = pref * (g2 * gsx - sdotp * gpx + sig / (P->W * P->W) * capx) + P->Gx;
+            double Fy = pref * (g2 * gsy - sdotp * gpy + sig / (P->W * P->W) * capy) + P->Gy;
             S->Fx[x] = Fx;
             S->Fy[x] = Fy;
 
@@ -502,7 +538,8 @@ API void orc_destroy(orc_state* S)
     if (!S) return;
     double** bufs[] = {&S->f, &S->g, &S->h, &S->f2, &S->g2, &S->h2, &S->jx0, &S->jy0,
                        &S->phi, &S->T, &S->ux, &S->uy, &S->pr, &S->Fx, &S->Fy,
-                       &S->dphx, &S->dphy, &S->lphi, &S->dTx, &S->dTy, &S->jx, &S->jy, &S->phipad, &S->Tpad};
+                       &S->dphx, &S->dphy, &S->lphi, &S->dTx, &S->dTy, &S->jx, &S->jy, &S->phipad, &S->Tpad,
+                       &S->mupad};
     for (size_t b = 0; b < sizeof(bufs) / sizeof(bufs[0]); ++b) free(*bufs[b]);
     free(S->writes);
     free(S);
@@ -516,6 +553,7 @@ API orc_state* orc_create(const orc_params* P, const double* phi0, const double*
                           const double* uy0, const double* T0)
 {
     if (!P || P->nx < 3 || P->ny < 3 || P->n_bubbles < 0 || P->n_bubbles > 4) return NULL;
+    if (P->force_form != 0 && P->force_form != 1) return NULL;
     if ((P->bc[XLO] == ORC_PERIODIC) != (P->bc[XHI] == ORC_PERIODIC)) return NULL;
     if ((P->bc[YLO] == ORC_PERIODIC) != (P->bc[YHI] == ORC_PERIODIC)) return NULL;
     orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
@@ -532,9 +570,11 @@ API orc_state* orc_create(const orc_params* P, const double* phi0, const double*
     S->dTx = xcalloc(n); S->dTy = xcalloc(n); S->jx = xcalloc(n); S->jy = xcalloc(n);
     S->phipad = xcalloc((size_t)(P->nx + 2) * (P->ny + 2));
     S->Tpad = xcalloc((size_t)(P->nx + 2) * (P->ny + 2));
+    S->mupad = xcalloc((size_t)(P->nx + 2) * (P->ny + 2));
     if (!S->f || !S->g || !S->h || !S->f2 || !S->g2 || !S->h2 || !S->jx0 || !S->jy0 || !S->phi ||
         !S->T || !S->ux || !S->uy || !S->pr || !S->Fx || !S->Fy || !S->dphx || !S->dphy ||
-        !S->lphi || !S->dTx || !S->dTy || !S->jx || !S->jy || !S->phipad || !S->Tpad) {
+        !S->lphi || !S->dTx || !S->dTy || !S->jx || !S->jy || !S->phipad || !S->Tpad ||
+        !S->mupad) {
         orc_destroy(S);
         return NULL;
     }

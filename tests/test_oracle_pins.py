@@ -510,3 +510,86 @@ def test_trt_reduces_to_bgk():
     o.set_state(**st, step=0)
     o.step(1)
     assert np.abs(o.get_state()["g"] - out[0]["g"]).max() > 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Potential form of the capillary force (force_form = 1)
+# ---------------------------------------------------------------------------
+
+def test_potential_form_total_force_equals_paper_form():
+    """On a periodic lattice the isotropic gradient stencil is antisymmetric,
+    so summation by parts gives sum mu grad phi = -sum phi grad mu exactly:
+    the potential form and the final form of Eq. 11 exert the same total
+    force (at uniform T, where the Marangoni terms vanish), node by node they
+    differ.  A dropped term of mu_phi, a wrong sign or a stencil applied to the
+    wrong field breaks the equality."""
+    nx, ny = 24, 20
+    p = wl.base_params(nx, ny)
+    p.update(bc=[wl.PERIODIC] * 4, sigma_ref=1e-2, sigma_T=-3e-4, W=2.5)
+    rng = np.random.default_rng(0)
+    i, j = wl.grid(nx, ny)
+    phi = wl.tanh_profile(np.hypot(i - 11.3, j - 9.6) - 6.0, 2.5) + 0.05 * rng.standard_normal((ny, nx))
+    T = np.full((ny, nx), 1.3)
+    out = []
+    for ff in (0, 1):
+        q = dict(p, force_form=ff)
+        out.append(oracle.Oracle(q, fields(phi, T=T)).macros_all())
+    scale = np.abs(out[1]["Fx"]).sum() + np.abs(out[1]["Fy"]).sum()
+    for k in ("Fx", "Fy"):
+        assert abs(out[0][k].sum() - out[1][k].sum()) <= 1e-13 * scale, k
+    assert np.abs(out[0]["Fx"] - out[1]["Fx"]).max() > 1e-3 * np.abs(out[0]["Fx"]).max()
+
+
+@pytest.mark.parametrize("force_form", [0, 1])
+def test_wall_ghosts_equal_mirror_image(force_form):
+    """Walls mirror phi (neutral wetting) and adiabatic walls mirror T, to any
+    distance: a walled lattice of height H must give the same pass-1 fields as
+    the periodic lattice of height 2H holding the state and its mirror image.
+    The potential form reads phi two nodes beyond the wall, so this pins the
+    second ghost ring as well."""
+    H, nx = 10, 16
+    rng = np.random.default_rng(2)
+    pw = wl.base_params(nx, H)
+    pw.update(bc=[wl.PERIODIC, wl.PERIODIC, wl.WALL_ADIABATIC, wl.WALL_ADIABATIC], sigma_ref=1e-2,
+              sigma_T=-2e-3, W=2.0, force_form=force_form)
+    pp = dict(pw, ny=2 * H, bc=[wl.PERIODIC] * 4)
+    i, j = wl.grid(nx, H)
+    ph = wl.tanh_profile(np.hypot(i - 7.2, j - 1.5) - 4.5, 2.0) + 0.02 * rng.standard_normal((H, nx))
+    T = 1 + 0.1 * np.cos(2 * np.pi * i / nx) + 0.01 * rng.standard_normal((H, nx))
+    mw = oracle.Oracle(pw, fields(ph, T=T)).macros_all()
+    mp = oracle.Oracle(pp, fields(np.concatenate([ph, ph[::-1]]), T=np.concatenate([T, T[::-1]]))).macros_all()
+    for k in ("Fx", "Fy", "ux", "uy", "p"):
+        assert np.abs(mw[k] - mp[k][:H]).max() <= 1e-15 * max(np.abs(mw[k]).max(), 1e-300), k
+
+
+def test_potential_form_laplace_law():
+    """Static drop at uniform T with the potential form: the scheme's pressure
+    p2 carries the capillary jump in the combination p2 + C phi mu_phi
+    (C = 3 sqrt2 sigma / (4 W), since mu grad phi = grad(phi mu) - phi grad mu),
+    whose jump is sigma / R (2-D Young-Laplace), within 5% at R = 16.  Its
+    spurious currents are below those of the final form of Eq. 11."""
+    L, R, W, sig = 64, 16.0, 3.0, 1e-2
+    i, j = wl.grid(L, L)
+    r = np.hypot(i - L / 2, j - L / 2)
+    umax = []
+    for ff in (0, 1):
+        p = single_phase(L, L, sigma_ref=sig, W=W, mu_h=0.1, mu_l=0.1, force_form=ff)
+        o = oracle.Oracle(p, fields(wl.tanh_profile(r - R, W), T=np.zeros((L, L))))
+        o.step(2000)
+        jump, um = [], []
+        for _ in range(10):
+            o.step(50)
+            F = o.fields()
+            phi = F["phi"]
+            lap = np.zeros_like(phi)
+            for k in range(1, 9):
+                w = 1 / 9 if k <= 4 else 1 / 36
+                lap += 6 * w * (np.roll(phi, (-CY[k], -CX[k]), (0, 1)) - phi)
+            mu = phi ** 3 - phi - W * W * lap
+            pt = F["p"] + (3 * math.sqrt(2) * sig / (4 * W)) * phi * mu * (ff == 1)
+            jump.append(pt[r < R - 6].mean() - pt[r > R + 8].mean())
+            um.append(np.hypot(F["ux"], F["uy"]).max())
+        if ff == 1:
+            assert abs(np.mean(jump) * R / sig - 1) < 0.05, np.mean(jump) * R / sig
+        umax.append(np.mean(um))
+    assert umax[1] < umax[0], umax
