@@ -46,6 +46,9 @@ extern "C" {
 /* Collision models (lbm_params.collision). */
 enum { LBM_BGK = 0, LBM_TRT = 1 };
 
+/* Forms of the capillary term of the interfacial force (lbm_params.force_form). */
+enum { LBM_FORCE_EQ11 = 0, LBM_FORCE_POTENTIAL = 1 };
+
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,     /* invalid argument or parameter set */
@@ -94,7 +97,13 @@ typedef struct lbm_params {
     uint32_t collision;    /* LBM_BGK: the single-relaxation-time collisions of Sec. 3;
                               LBM_TRT: two relaxation times for the NS and thermal LBEs
                               (the extension Sec. 3 names), see trt_magic */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t force_form;   /* capillary term of the interfacial force F_s of Eq. 11:
+                              LBM_FORCE_EQ11: (sigma/W^2) mu_phi grad phi, the paper's
+                              final form; LBM_FORCE_POTENTIAL: -(sigma/W^2) phi grad mu_phi,
+                              equal up to a gradient (absorbed by the pressure, which then
+                              lacks the jump sigma/W^2 * 3 sqrt2 W/4 * phi mu_phi); mu_phi on
+                              the one-node ring takes phi extended to a second ring by the
+                              same ghost rules */
     /* fluid properties; _l: light (phi = -1), _h: heavy (phi = +1); each is
        interpolated linearly in phi (Sec. 4 preamble).  mu is the dynamic
        viscosity, lambda the conductivity, rhocp the heat capacitance rho*c_p. */

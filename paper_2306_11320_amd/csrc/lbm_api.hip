@@ -67,7 +67,8 @@ int validate(const lbm_params& p)
         return fail(LBM_EINVAL, "y sides: periodic paired with a non-periodic side");
     if (p.grad_mode > 1) return fail(LBM_EINVAL, "grad_mode must be 0 or 1");
     if (p.collision != LBM_BGK && p.collision != LBM_TRT) return fail(LBM_EINVAL, "unknown collision %u", p.collision);
-    if (p.reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+    if (p.force_form != LBM_FORCE_EQ11 && p.force_form != LBM_FORCE_POTENTIAL)
+        return fail(LBM_EINVAL, "unknown force_form %u", p.force_form);
     if (p.collision == LBM_TRT && !(p.trt_magic > 0)) return fail(LBM_EINVAL, "trt_magic must be positive");
     if (p.n_bubbles > 4) return fail(LBM_EINVAL, "at most 4 tracked regions");
     if (!(p.rho_l > 0 && p.rho_h > 0)) return fail(LBM_EINVAL, "densities must be positive");
@@ -119,6 +120,7 @@ lbm::Inst<real> make_inst(const lbm_params& p, const Layout& L, char* ws)
     I.plane = L.plane;
     I.grad_mode = (int)p.grad_mode;
     I.collision = (int)p.collision;
+    I.force_form = (int)p.force_form;
     I.trt_magic = (real)p.trt_magic;
     for (int s = 0; s < 4; ++s) I.bc[s] = (int)p.bc[s];
     const double phi0 = p.phi0_dev, T0 = p.T0_dev;
@@ -179,7 +181,9 @@ struct lbm_ctx {
     int tile = 0;
     int graph_steps = 64;
     int grid = 0;
-    int any_trt = 0;  // some lattice relaxes with two relaxation times
+    // step kernel: 0 BGK only; 1 some lattice relaxes with two relaxation
+    // times; 2 some lattice uses the potential form of the capillary force
+    int variant = 0;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -247,7 +251,7 @@ void drop_graph(lbm_ctx* c)
 int launch_one(lbm_ctx* c, int src)
 {
     HIP_TRY(lbm::launch_step((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile], c->ntiles[c->tile], c->grid, src,
-                             c->any_trt, c->stream));
+                             c->variant, c->stream));
     return LBM_OK;
 }
 
@@ -301,8 +305,10 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     c->ws = static_cast<char*>(d_ws);
     c->ws_bytes = ws_bytes;
     c->params.assign(ps, ps + n);
-    for (int k = 0; k < n; ++k)
-        if (ps[k].collision == LBM_TRT) c->any_trt = 1;
+    for (int k = 0; k < n; ++k) {
+        if (ps[k].collision == LBM_TRT && c->variant < 1) c->variant = 1;
+        if (ps[k].force_form == LBM_FORCE_POTENTIAL) c->variant = 2;
+    }
     c->lay = lay;
     c->grid = n > 1 ? -1 : 0;  // batched: persistent grid sized at the first step
     c->d_insts = c->ws + off_insts;
@@ -817,7 +823,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
         int grids[3] = {0, 0, 0}, ng = 1;
         if (c->n > 1) {
             int per_cu = 1;
-            if (lbm::step_occupancy((int)c->prec, t, c->any_trt, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+            if (lbm::step_occupancy((int)c->prec, t, c->variant, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
             const int resident = per_cu * (cus > 0 ? cus : 256);
             grids[0] = resident < c->ntiles[t] ? resident : c->ntiles[t];
             grids[1] = 2 * resident < c->ntiles[t] ? 2 * resident : c->ntiles[t];

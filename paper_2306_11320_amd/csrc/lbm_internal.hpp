@@ -28,6 +28,7 @@ struct Inst {
     real* jbase[2];
     int nx, ny, pitch, grad_mode;
     int collision;       // 0: BGK; 1: two relaxation times for g and h
+    int force_form;      // 0: mu_phi grad phi (Eq. 11); 1: -phi grad mu_phi
     real trt_magic;      // (tau+ - 1/2)(tau- - 1/2)
     long long plane;
     int bc[4];
@@ -75,9 +76,11 @@ constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128};
 constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4};
 
 // Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
+// `variant` selects the step kernel: 0 BGK only; 1 BGK or two relaxation
+// times per lattice; 2 also the potential form of the capillary force (every
+// tile through the general boundary path).
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
-                       int any_trt,
-                       hipStream_t s);
+                       int variant, hipStream_t s);
 // Macroscopic fields of level `src`: any output may be null; out_f32 selects
 // float outputs.  If `jprev_out` is set, (phi u) is written to the lattice's
 // jprev planes instead.
@@ -98,7 +101,7 @@ hipError_t launch_diag(int prec, int tile, const void* insts, const Tile* tiles,
                        const DiagArgs& a, double* partials, double* result, hipStream_t s);
 
 // Resident workgroups of the step kernel per compute unit.
-hipError_t step_occupancy(int prec, int tile, int any_trt, int* blocks_per_cu);
+hipError_t step_occupancy(int prec, int tile, int variant, int* blocks_per_cu);
 
 // Plain 16-byte-vector copy of `bytes` (a multiple of 16).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

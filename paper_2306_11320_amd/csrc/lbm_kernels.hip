@@ -91,6 +91,17 @@ struct Patch {
     real h[9][NP];   // h_i - w_i T0 of the node (real nodes only)
 };
 
+// Extra LDS of the potential form of the capillary force: phi - phi0 on the
+// tile and two rings, and mu_phi on the tile and one ring (the layout of the
+// patch's arrays).
+template <typename real, int TX, int TY>
+struct PotLDS {
+    static constexpr int QX = TX + 4, QY = TY + 4;
+    real phw[QX * QY];
+    real mu[(TX + 2) * (TY + 2)];
+};
+struct NoPot {};
+
 // Wall temperature relative to T0 at coordinate s along `side`.
 template <typename real>
 __device__ inline real wall_T(const Inst<real>& I, int side, real s)
@@ -240,6 +251,50 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     return inside;
 }
 
+// phi - phi0 at lattice point (gx, gy), at most two nodes outside the lattice,
+// with the ghost rules applied.
+template <typename real>
+__device__ inline real phi_at(const Inst<real>& I, int src, int gx, int gy)
+{
+    int sx, sy;
+    real aphi, sphi, aT, sT;
+    const bool rn = resolve(I, gx, gy, sx, sy, aphi, sphi, aT, sT);
+    const unsigned idx = (unsigned)(sy * I.pitch + sx);
+    real sf = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sf += ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
+    (void)aT; (void)sT;
+    return rn ? sf : aphi + sphi * sf;
+}
+
+// Potential form: mu_phi = phi^3 - phi - W^2 lap phi on the tile and its ring.
+// The ring's Laplacian reads phi on a second ring (outer entries loaded here,
+// ghost rules as for the first ring).  Every work-item of the workgroup calls
+// this after load_patch (it synchronizes).
+template <typename real, int TX, int TY>
+__device__ inline void fill_mu(const Inst<real>& I, int src, const Patch<real, TX, TY>& S, PotLDS<real, TX, TY>& Q,
+                               int x0, int y0)
+{
+    constexpr int PX = TX + 2, PY = TY + 2, QX = TX + 4, QY = TY + 4;
+    for (int q = threadIdx.x; q < QX * QY; q += TX * TY) {
+        const int qx = q % QX, qy = q / QX;
+        const bool inner = qx >= 1 && qx <= PX && qy >= 1 && qy <= PY;
+        Q.phw[q] = inner ? S.phi[(qy - 1) * PX + (qx - 1)] : phi_at(I, src, x0 + qx - 2, y0 + qy - 2);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < PX * PY; q += TX * TY) {
+        const int c = (q / PX + 1) * QX + (q % PX + 1);
+        const real pc = Q.phw[c];
+        const real lap = real(2.0 / 3.0) * ((Q.phw[c + 1] + Q.phw[c - 1]) + (Q.phw[c + QX] + Q.phw[c - QX]) - real(4) * pc)
+                       + real(1.0 / 6.0) * ((Q.phw[c + QX + 1] + Q.phw[c + QX - 1]) + (Q.phw[c - QX - 1] + Q.phw[c - QX + 1])
+                                            - real(4) * pc);
+        const real phi = I.phi0 + pc;
+        const real pm1 = (I.phi0 - real(1)) + pc;
+        Q.mu[q] = pm1 * (phi + real(1)) * phi - I.W2 * lap;
+    }
+    __syncthreads();
+}
+
 template <typename real>
 struct Macro {
     real dphi, phi, theta;
@@ -247,10 +302,13 @@ struct Macro {
     real rho, ux, uy, p, Fx, Fy, grx, gry, irho;
 };
 
-// Pass-1 quantities of one node from the patch and its own g_i.
-template <typename real, int PX>
+// Pass-1 quantities of one node from the patch and its own g_i.  POT: the
+// lattice may use the potential form of the capillary force, with mu_phi of the
+// patch in smu.
+template <typename real, int PX, bool POT = false>
 __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __restrict__ sphi,
-                                          const real* __restrict__ sT, int c, const real (&g)[9])
+                                          const real* __restrict__ sT, int c, const real (&g)[9],
+                                          const real* __restrict__ smu = nullptr)
 {
     Macro<real> m;
     const real pc = sphi[c];
@@ -286,9 +344,20 @@ __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __res
     // F_s = 3 sqrt2 W/4 [|grad phi|^2 grad sigma - (grad sigma . grad phi) grad phi + sigma/W^2 mu_phi grad phi]
     const real g2 = m.gpx * m.gpx + m.gpy * m.gpy;
     const real sdp = gsx * m.gpx + gsy * m.gpy;
-    const real cap = sig * I.inv_W2 * mu_phi;
-    m.Fx = I.pref * (g2 * gsx + (cap - sdp) * m.gpx) + I.Gx;
-    m.Fy = I.pref * (g2 * gsy + (cap - sdp) * m.gpy) + I.Gy;
+    if (POT && I.force_form == 1) {
+        // potential form: -phi grad mu_phi in place of mu_phi grad phi
+        const real mE = smu[c + 1], mW = smu[c - 1], mN = smu[c + PX], mS = smu[c - PX];
+        const real mNE = smu[c + PX + 1], mNW = smu[c + PX - 1], mSW = smu[c - PX - 1], mSE = smu[c - PX + 1];
+        const real gmx = third * (mE - mW) + twelfth * ((mNE - mNW) + (mSE - mSW));
+        const real gmy = third * (mN - mS) + twelfth * ((mNE + mNW) - (mSW + mSE));
+        const real sp = sig * I.inv_W2 * phi;
+        m.Fx = I.pref * (g2 * gsx - sdp * m.gpx - sp * gmx) + I.Gx;
+        m.Fy = I.pref * (g2 * gsy - sdp * m.gpy - sp * gmy) + I.Gy;
+    } else {
+        const real cap = sig * I.inv_W2 * mu_phi;
+        m.Fx = I.pref * (g2 * gsx + (cap - sdp) * m.gpx) + I.Gx;
+        m.Fy = I.pref * (g2 * gsy + (cap - sdp) * m.gpy) + I.Gy;
+    }
     // rho u = sum c_i g_i + F/2
     const real mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const real my = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
@@ -475,9 +544,10 @@ __device__ __forceinline__ void collide_dir(const Inst<real>& I, const Macro<rea
 // populations are f, g, h.  The thermal update at the destination y = x + c_i
 // is h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y).
 // Each direction is stored as soon as it is collided.
-template <typename real, int TX, int TY, bool EDGE, bool TRT>
-__device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<real, TX, TY>& S, int gi, int gj, int c,
-                                            int dst, const real (&f)[9], const real (&g)[9], const real (&h)[9])
+template <typename real, int TX, int TY, bool EDGE, bool TRT, bool POT>
+__device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<real, TX, TY>& S, const real* smu, int gi,
+                                            int gj, int c, int dst, const real (&f)[9], const real (&g)[9],
+                                            const real (&h)[9])
 {
     constexpr int PX = Patch<real, TX, TY>::PX;
     const unsigned own = (unsigned)(gj * I.pitch + gi);
@@ -494,7 +564,7 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
         dcol[2] = (unsigned)wrap1(gi + 1, I.nx);
     }
 
-    const Macro<real> m = node_macros<real, PX>(I, S.phi, S.T, c, g);
+    const Macro<real> m = node_macros<real, PX, POT>(I, S.phi, S.T, c, g, smu);
     real jx, jy;
     const Pre<real> q = pre_collide<real, TRT>(I, m, f, h, jpx, jpy, jx, jy);
     st(Jx, own * (unsigned)sizeof(real), jx);
@@ -552,16 +622,24 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
     }
 }
 
-// One node per work-item.
-template <typename real, int TX, int TY, bool EDGE, bool WHOLE, bool TRT>
-__device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S)
+// One node per work-item.  POT (with QT = PotLDS): the lattice may use the
+// potential form of the capillary force.
+template <typename real, int TX, int TY, bool EDGE, bool WHOLE, bool TRT, bool POT = false, typename QT = NoPot>
+__device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S,
+                                          QT& Q)
 {
     real f[9], g[9], h[9];
     const bool inside = load_patch<real, TX, TY, EDGE, WHOLE>(I, src, S, x0, y0, f, g, h);
+    const real* smu = nullptr;
+    if constexpr (POT) {
+        // uniform branch: every work-item reaches the barriers of fill_mu
+        if (I.force_form == 1) fill_mu<real, TX, TY>(I, src, S, Q, x0, y0);
+        smu = Q.mu;
+    }
     if (!inside) return;
     const int tid = threadIdx.x;
     const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-    node_update<real, TX, TY, EDGE, TRT>(I, S, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h);
+    node_update<real, TX, TY, EDGE, TRT, POT>(I, S, smu, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h);
 }
 
 // Interior tiles take the wrap-only path; a whole one needs no per-node
@@ -570,11 +648,12 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
 template <typename real, int TX, int TY, bool TRT>
 __device__ __forceinline__ void tile_any(const Inst<real>& I, const Tile& tl, int src, Patch<real, TX, TY>& S)
 {
+    NoPot none;
     if (tl.flags & kTileInterior) {
-        if (tl.flags & kTileWhole) tile_step<real, TX, TY, false, true, TRT>(I, tl.x0, tl.y0, src, S);
-        else tile_step<real, TX, TY, false, false, TRT>(I, tl.x0, tl.y0, src, S);
+        if (tl.flags & kTileWhole) tile_step<real, TX, TY, false, true, TRT>(I, tl.x0, tl.y0, src, S, none);
+        else tile_step<real, TX, TY, false, false, TRT>(I, tl.x0, tl.y0, src, S, none);
     } else {
-        tile_step<real, TX, TY, true, false, TRT>(I, tl.x0, tl.y0, src, S);
+        tile_step<real, TX, TY, true, false, TRT>(I, tl.x0, tl.y0, src, S, none);
     }
 }
 
@@ -602,12 +681,16 @@ __device__ inline void my_tiles(int ntiles, int& t0, int& t1)
 }
 
 // One step of every tile in the table, one node per work-item.
-// ANY_TRT: some lattice of the launch uses two relaxation times (a separate
-// kernel, so that the BGK-only kernel keeps its own register budget).
-template <typename real, int TX, int TY, bool ANY_TRT>
+// VAR 0: every lattice of the launch uses BGK and the capillary term of Eq. 11;
+// VAR 1: some lattice uses two relaxation times; VAR 2: some lattice uses the
+// potential form of the capillary force: every tile takes the general boundary
+// path and the extra LDS.  Separate kernels, so that the BGK-only kernel keeps
+// its own register budget.
+template <typename real, int TX, int TY, int VAR>
 __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
                                                   int ntiles, int src)
 {
+    constexpr bool ANY_TRT = VAR >= 1;
     __shared__ Patch<real, TX, TY> S;
     int t0, t1;
     my_tiles(ntiles, t0, t1);
@@ -619,8 +702,14 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
         tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
         tl.flags = __builtin_amdgcn_readfirstlane(tl.flags);
         const Inst<real>& I = insts[tl.inst];
-        if (!ANY_TRT || I.collision == 0) tile_any<real, TX, TY, false>(I, tl, src, S);
-        else tile_any<real, TX, TY, true>(I, tl, src, S);
+        if constexpr (VAR == 2) {
+            __shared__ PotLDS<real, TX, TY> Q;
+            if (I.collision == 0) tile_step<real, TX, TY, true, false, false, true>(I, tl.x0, tl.y0, src, S, Q);
+            else tile_step<real, TX, TY, true, false, true, true>(I, tl.x0, tl.y0, src, S, Q);
+        } else {
+            if (!ANY_TRT || I.collision == 0) tile_any<real, TX, TY, false>(I, tl, src, S);
+            else tile_any<real, TX, TY, true>(I, tl, src, S);
+        }
         if (t + 1 < t1) __syncthreads();
     }
 }
@@ -637,6 +726,7 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
                                                     void* op, int out_f32, int jprev_out)
 {
     __shared__ Patch<real, TX, TY> S;
+    __shared__ PotLDS<real, TX, TY> Q;
     int t0, t1;
     my_tiles(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
@@ -644,11 +734,12 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = load_any(I, tl, src, S, f, g, h);
+        if (I.force_form == 1) fill_mu<real, TX, TY>(I, src, S, Q, tl.x0, tl.y0);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
             const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX>(I, S.phi, S.T, c, g);
+            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX, true>(I, S.phi, S.T, c, g, Q.mu);
             if (jprev_out) {
                 const long long own = (long long)gj * I.pitch + gi;
                 const gptr<real> J = to_global(I.jprev);
@@ -777,6 +868,7 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
                                                   double* __restrict__ partials)
 {
     __shared__ Patch<real, TX, TY> S;
+    __shared__ PotLDS<real, TX, TY> Q;
     __shared__ double red[(TX * TY) / 64][D_COUNT];
     double acc[D_COUNT];
 #pragma unroll
@@ -788,11 +880,12 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         const Inst<real>& I = insts[tl.inst];
         real f[9], g[9], h[9];
         const bool inside = load_any(I, tl, src, S, f, g, h);
+        if (I.force_form == 1) fill_mu<real, TX, TY>(I, src, S, Q, tl.x0, tl.y0);
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
             const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX>(I, S.phi, S.T, c, g);
+            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX, true>(I, S.phi, S.T, c, g, Q.mu);
             const double phi = (double)I.phi0 + (double)m.dphi;
             const double T = (double)I.T0 + (double)m.theta;
             const double ux = m.ux, uy = m.uy, p = m.p;
@@ -894,16 +987,17 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 // ---- launchers ----
 
 template <typename real, int TX, int TY>
-static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, int any_trt,
+static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, int variant,
                          hipStream_t s)
 {
     const int G = grid > 0 ? grid : ntiles;
-    if (any_trt)
-        hipLaunchKernelGGL((k_step<real, TX, TY, true>), dim3(G), dim3(TX * TY), 0, s,
-                           static_cast<const Inst<real>*>(insts), tiles, ntiles, src);
+    const Inst<real>* ip = static_cast<const Inst<real>*>(insts);
+    if (variant == 2)
+        hipLaunchKernelGGL((k_step<real, TX, TY, 2>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_step<real, TX, TY, 1>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
     else
-        hipLaunchKernelGGL((k_step<real, TX, TY, false>), dim3(G), dim3(TX * TY), 0, s,
-                           static_cast<const Inst<real>*>(insts), tiles, ntiles, src);
+        hipLaunchKernelGGL((k_step<real, TX, TY, 0>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
     return hipGetLastError();
 }
 
@@ -942,10 +1036,10 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     }
 
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
-                       int any_trt, hipStream_t s)
+                       int variant, hipStream_t s)
 {
-#define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, any_trt, s)
-#define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, any_trt, s)
+#define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, variant, s)
+#define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, variant, s)
     if (prec == 0) { LBM_TILE_SWITCH(tile, STEP64) }
     LBM_TILE_SWITCH(tile, STEP32)
 #undef STEP64
@@ -953,16 +1047,17 @@ hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles,
 }
 
 template <typename real, int TX, int TY>
-static hipError_t occ_t(int* blocks, int any_trt)
+static hipError_t occ_t(int* blocks, int variant)
 {
-    if (any_trt) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, true>, TX * TY, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, false>, TX * TY, 0);
+    if (variant == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 2>, TX * TY, 0);
+    if (variant == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 1>, TX * TY, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 0>, TX * TY, 0);
 }
 
-hipError_t step_occupancy(int prec, int tile, int any_trt, int* blocks_per_cu)
+hipError_t step_occupancy(int prec, int tile, int variant, int* blocks_per_cu)
 {
-#define O64(a, b) occ_t<double, a, b>(blocks_per_cu, any_trt)
-#define O32(a, b) occ_t<float, a, b>(blocks_per_cu, any_trt)
+#define O64(a, b) occ_t<double, a, b>(blocks_per_cu, variant)
+#define O32(a, b) occ_t<float, a, b>(blocks_per_cu, variant)
     if (prec == 0) { LBM_TILE_SWITCH(tile, O64) }
     LBM_TILE_SWITCH(tile, O32)
 #undef O64

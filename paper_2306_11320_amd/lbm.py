@@ -20,6 +20,7 @@ ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_ENOSPACE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_DEV = 0, 1
 BGK, TRT = 0, 1
+FORCE_EQ11, FORCE_POTENTIAL = 0, 1
 OUT_F64, OUT_F32 = 0, 1
 
 EXPORTED = [
@@ -45,7 +46,7 @@ class Params(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("nx", C.c_uint32), ("ny", C.c_uint32), ("precision", C.c_uint32),
         ("bc", C.c_uint32 * 4), ("grad_mode", C.c_uint32), ("n_bubbles", C.c_uint32),
-        ("collision", C.c_uint32), ("reserved", C.c_uint32),
+        ("collision", C.c_uint32), ("force_form", C.c_uint32),
         ("rho_l", C.c_double), ("rho_h", C.c_double), ("mu_l", C.c_double), ("mu_h", C.c_double),
         ("lambda_l", C.c_double), ("lambda_h", C.c_double), ("rhocp_l", C.c_double), ("rhocp_h", C.c_double),
         ("sigma_ref", C.c_double), ("sigma_T", C.c_double), ("sigma_TT", C.c_double), ("T_ref", C.c_double),
@@ -146,6 +147,7 @@ def make_params(cfg: dict, precision: int = FP64) -> Params:
         p.Tw_slope[s] = float(cfg.get("tw_slope", [0.0] * 4)[s])
     p.grad_mode = int(cfg.get("grad_mode", 0))
     p.collision = int(cfg.get("collision", 0))
+    p.force_form = int(cfg.get("force_form", 0))
     p.trt_magic = float(cfg.get("trt_magic", 3.0 / 16.0))
     bx, by = list(cfg.get("bubbles_x", [])), list(cfg.get("bubbles_y", []))
     p.n_bubbles = len(bx)

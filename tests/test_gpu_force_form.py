@@ -1,0 +1,184 @@
+"""Potential form of the capillary force (force_form = 1): the HIP path against
+the FP64 oracle, through the C ABI.
+
+The capillary term of Eq. 11, (sigma/W^2) mu_phi grad phi, is replaced by
+-(sigma/W^2) phi grad mu_phi; mu_phi on the one-node ring reads phi on a second
+ring of ghosts.  Tolerances as for the paper's form: FP64 one step max |diff|
+<= 2e-13 of the population family's scale, relative L2 <= 1e-10 per field
+after many steps; FP32 deviation storage phi and T - T0 <= 1e-4, u (normalised
+by max |u|) <= 1e-3; launch shapes and batching bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_11320_amd import workloads as wl
+from tests.conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_2306_11320_amd.lbm")
+
+ONE_STEP_TOL = 2e-13
+MULTI_STEP_TOL = 1e-10
+
+
+def potential(cfg):
+    cfg = dict(cfg)
+    cfg["force_form"] = lbm.FORCE_POTENTIAL
+    return cfg
+
+
+def perturbed_state(cfg, f0, seed):
+    o = oracle.Oracle(cfg, f0)
+    st = o.get_state()
+    d = wl.perturbation(cfg["nx"], cfg["ny"], seed=seed)
+    st = {k: st[k] + d[k] for k in ("f", "g", "h", "jprev")}
+    o.set_state(**st, step=0)
+    return o, st
+
+
+def rel_l2(a, b, scale=None):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sqrt(np.sum(b * b)) if scale is None else scale * np.sqrt(b.size)
+    return float(np.sqrt(np.sum((a - b) ** 2)) / (den if den > 0 else 1.0))
+
+
+def compare_pops(gpu_st, orc_st, tol):
+    for fam in ("f", "g", "h", "jprev"):
+        ref = orc_st[fam]
+        scale = max(np.abs(ref).max(), 1e-300)
+        err = np.abs(gpu_st[fam] - ref).max() / scale
+        assert err <= tol, f"{fam}: max rel diff {err:.3e} > {tol:.1e}"
+
+
+@pytest.mark.parametrize("bcs", wl.ALL_BCS, ids=lambda b: "bc" + "".join(map(str, b)))
+@pytest.mark.parametrize("shape", [(70, 13), (5, 4), (133, 41)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_one_step_fp64(bcs, shape):
+    nx, ny = shape
+    cfg, f0 = wl.tiny(nx, ny, bc=bcs, seed=nx + ny)
+    cfg = potential(cfg)
+    announce("potential_one_step_fp64", bcs, shape)
+    o, st = perturbed_state(cfg, f0, seed=7)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.set_state(0, **st, step=0)
+    o.step(1)
+    lat.step(1)
+    compare_pops(lat.get_state(), o.get_state(), ONE_STEP_TOL)
+    lat.close()
+
+
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[0], wl.ALL_BCS[4]], ids=["periodic", "inlet"])
+def test_one_step_trt_grad_mode1_fp64(bcs):
+    """The potential form together with two relaxation times and the stencil
+    normal (grad_mode 1)."""
+    cfg, f0 = wl.tiny(70, 29, bc=bcs, seed=21)
+    cfg = potential(cfg)
+    cfg.update(collision=lbm.TRT, trt_magic=0.25, grad_mode=1)
+    announce("potential_one_step_trt", bcs)
+    o, st = perturbed_state(cfg, f0, seed=5)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.set_state(0, **st, step=0)
+    o.step(1)
+    lat.step(1)
+    compare_pops(lat.get_state(), o.get_state(), ONE_STEP_TOL)
+    lat.close()
+
+
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[1], wl.ALL_BCS[4]], ids=["channel", "inlet"])
+def test_multistep_fp64_fields_and_diagnostics(bcs):
+    cfg, f0 = wl.tiny(96, 72, bc=bcs, seed=5)
+    cfg = potential(cfg)
+    announce("potential_multistep_fp64", bcs)
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    for _ in range(3):
+        o.step(100)
+        lat.step(100)
+        ref, got = o.fields(), lat.fields()
+        for k in ("phi", "ux", "uy", "T", "p"):
+            e = rel_l2(got[k], ref[k])
+            assert e <= MULTI_STEP_TOL, f"{k}: rel L2 {e:.3e}"
+    a, b = lat.diagnostics(), o.diagnostics()
+    for k in ("mass_phi", "heat", "u_r", "ux_r", "max_u"):
+        assert abs(a[k] - b[k]) <= 1e-10 * max(abs(b[k]), 1e-12), (k, a[k], b[k])
+    lat.close()
+
+
+@pytest.mark.parametrize("bcs", [wl.ALL_BCS[1], wl.ALL_BCS[4]], ids=["channel", "inlet"])
+def test_fp32_dev_vs_oracle(bcs):
+    cfg, f0 = wl.tiny(96, 72, bc=bcs, seed=3)
+    cfg = potential(cfg)
+    announce("potential_fp32_dev", bcs)
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+    T0 = cfg["T_ref"]
+    for _ in range(2):
+        o.step(500)
+        lat.step(500)
+        got, ref = lat.fields(), o.fields()
+        assert rel_l2(got["phi"], ref["phi"]) <= 1e-4
+        assert rel_l2(got["T"] - T0, ref["T"] - T0) <= 1e-4
+        umax = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max())
+        for k in ("ux", "uy"):
+            assert rel_l2(got[k], ref[k], scale=umax) <= 1e-3, k
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32_DEV"])
+def test_tile_shapes_bitwise(prec):
+    """Every tile shape gives bitwise the same state (walls, inlet, outlet and
+    tiles cut by the lattice's end)."""
+    cfg, f0 = wl.tiny(150, 45, bc=wl.ALL_BCS[4], seed=2)
+    cfg = potential(cfg)
+    announce("potential_tile_shapes", prec)
+    ref = None
+    for t in range(len(lbm.tile_shapes())):
+        lat = lbm.Lattice(cfg, f0, getattr(lbm, prec))
+        lat.set_tile(t)
+        lat.step(21)
+        st = lat.get_state()
+        lat.close()
+        if ref is None:
+            ref = st
+        else:
+            for k in ("f", "g", "h", "jprev"):
+                assert np.array_equal(st[k], ref[k]), f"tile {t}: {k} differs"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mixed_force_form_batch_bitwise(prec):
+    """A batch with one potential-form lattice runs the general kernel for all
+    of its lattices: each equals the same lattice run alone, bitwise."""
+    P = lbm.FP64 if prec == "fp64" else lbm.FP32_DEV
+    items = [wl.tiny(70, 33, bc=wl.ALL_BCS[1], seed=1), wl.tiny(131, 64, bc=wl.ALL_BCS[4], seed=2),
+             wl.tiny(96, 40, bc=wl.ALL_BCS[0], seed=3)]
+    items[1] = (potential(items[1][0]), items[1][1])
+    items[2][0]["collision"] = lbm.TRT
+    announce("mixed_force_form_batch", prec)
+    batch = lbm.Lattice.batch(items, P)
+    batch.step(29)
+    for k, (cfg, f0) in enumerate(items):
+        single = lbm.Lattice(cfg, f0, P)
+        single.step(29)
+        sa, sb = batch.get_state(k), single.get_state()
+        for fam in ("f", "g", "h", "jprev"):
+            assert np.array_equal(sa[fam], sb[fam]), (k, fam)
+        single.close()
+    batch.close()
+
+
+def test_full_size_one_step_fp64():
+    """One step of the potential form at the droplet workload's full size
+    (256 x 1024) from a perturbed equilibrium, every population compared."""
+    cfg, f0 = wl.droplet(Ma=1.0, ratio=0.5)
+    cfg = potential(cfg)
+    announce("potential_full_size_one_step", cfg["nx"], cfg["ny"])
+    o, st = perturbed_state(cfg, f0, seed=3)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    lat.set_state(0, **st, step=0)
+    o.step(1)
+    lat.step(1)
+    compare_pops(lat.get_state(), o.get_state(), ONE_STEP_TOL)
+    lat.close()

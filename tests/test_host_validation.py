@@ -49,7 +49,7 @@ def test_valid_lattice_workspace():
     (dict(bc=[wl.PERIODIC, wl.WALL_T, wl.WALL_T, wl.WALL_T]), "periodic paired"),
     (dict(grad_mode=2), "grad_mode"),
     (dict(collision=2), "collision"),
-    (dict(reserved=1), "reserved"),
+    (dict(force_form=2), "force_form"),
     (dict(collision=lbm.TRT, trt_magic=0.0), "trt_magic"),
     (dict(n_bubbles=5), "tracked regions"),
     (dict(rho_l=0.0), "densities"),
