@@ -202,8 +202,26 @@ __device__ inline void fill_entry(const Inst<real>& I, int src, Patch<real, TX, 
     (void)aphi; (void)sphi; (void)aT; (void)sT;
 }
 
+// Tile coordinates (hx, hy) of ring entry q: the row below, the row above,
+// then the left and right columns.
+template <int TX, int TY>
+__device__ inline void ring_coords(int q, int& hx, int& hy)
+{
+    constexpr int PX = TX + 2;
+    if (q < PX) { hx = q - 1; hy = -1; }
+    else if (q < 2 * PX) { hx = q - PX - 1; hy = TY; }
+    else {
+        const int r = q - 2 * PX;
+        hx = r < TY ? -1 : TX;
+        hy = r < TY ? r : r - TY;
+    }
+}
+
 // Loads the work-item's own node and fills the patch.  Returns whether the
-// work-item's node lies in the lattice.
+// work-item's node lies in the lattice.  In interior tiles the first TX*TY
+// ring entries go one per work-item, and their loads are issued together with
+// the node's own, so that the workgroup waits for one memory round trip before
+// the barrier, not two.
 template <typename real, int TX, int TY, bool EDGE, bool WHOLE>
 __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int x0,
                                   int y0, real (&f)[9], real (&g)[9], real (&h)[9])
@@ -214,6 +232,23 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     const int gi = x0 + lx, gj = y0 + ly;
     const bool inside = WHOLE || (gi < I.nx && gj < I.ny);
     const int c = (ly + 1) * PT::PX + (lx + 1);
+
+    // ring entry `tid` of an interior tile (at most a periodic wrap): source
+    // node and loads; edge tiles fill their ring after the node's own loads
+    const bool ring = !EDGE && tid < PT::NRING;
+    int rc = 0;
+    real rf[9], rh[9];
+    if (ring) {
+        int hx, hy;
+        ring_coords<TX, TY>(tid, hx, hy);
+        rc = (hy + 1) * PT::PX + (hx + 1);
+        const unsigned ridx = (unsigned)(wrap1(y0 + hy, I.ny) * I.pitch + wrap1(x0 + hx, I.nx));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            rf[k] = ld(src_plane(I, src, kF + k), ridx * (unsigned)sizeof(real));
+            rh[k] = ld(src_plane(I, src, kH + k), ridx * (unsigned)sizeof(real));
+        }
+    }
     if (inside) {
         const unsigned idx = (unsigned)(gj * I.pitch + gi);
         real sf = 0, sh = 0;
@@ -236,15 +271,24 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     } else {
         fill_entry<real, TX, TY, EDGE>(I, src, S, c, gi, gj);
     }
-    for (int q = tid; q < PT::NRING; q += TX * TY) {
-        int hx, hy;
-        if (q < PT::PX) { hx = q - 1; hy = -1; }
-        else if (q < 2 * PT::PX) { hx = q - PT::PX - 1; hy = TY; }
-        else {
-            const int r = q - 2 * PT::PX;
-            hx = r < TY ? -1 : TX;
-            hy = r < TY ? r : r - TY;
+    if (ring) {
+        real sf = 0, sh = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sf += rf[k];
+            sh += rh[k];
         }
+        S.phi[rc] = sf;
+        S.T[rc] = sh;
+        S.irc[rc] = recip(I.rcp_a + I.rcp_b * (I.phi0 + sf));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S.h[k][rc] = rh[k];
+    }
+    // the remaining ring entries: all of an edge tile's, and those beyond one
+    // per work-item
+    for (int q = EDGE ? tid : tid + TX * TY; q < PT::NRING; q += TX * TY) {
+        int hx, hy;
+        ring_coords<TX, TY>(q, hx, hy);
         fill_entry<real, TX, TY, EDGE>(I, src, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
     }
     __syncthreads();
