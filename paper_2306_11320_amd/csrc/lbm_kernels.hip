@@ -224,7 +224,7 @@ __device__ inline void ring_coords(int q, int& hx, int& hy)
 // the barrier, not two.
 template <typename real, int TX, int TY, bool EDGE, bool WHOLE>
 __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int x0,
-                                  int y0, real (&f)[9], real (&g)[9], real (&h)[9])
+                                  int y0, real (&f)[9], real (&g)[9], real (&h)[9], real& jpx, real& jpy)
 {
     using PT = Patch<real, TX, TY>;
     const int tid = threadIdx.x;
@@ -258,6 +258,9 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
             h[k] = ld(src_plane(I, src, kH + k), idx * (unsigned)sizeof(real));
             g[k] = ld(src_plane(I, src, kG + k), idx * (unsigned)sizeof(real));
         }
+        // (phi u) of the previous level, needed after the barrier
+        jpx = ld(to_global<const real>(I.jbase[0]), idx * (unsigned)sizeof(real));
+        jpy = ld(to_global<const real>(I.jbase[1]), idx * (unsigned)sizeof(real));
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             sf += f[k];
@@ -591,12 +594,11 @@ __device__ __forceinline__ void collide_dir(const Inst<real>& I, const Macro<rea
 template <typename real, int TX, int TY, bool EDGE, bool TRT, bool POT>
 __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<real, TX, TY>& S, const real* smu, int gi,
                                             int gj, int c, int dst, const real (&f)[9], const real (&g)[9],
-                                            const real (&h)[9])
+                                            const real (&h)[9], real jpx, real jpy)
 {
     constexpr int PX = Patch<real, TX, TY>::PX;
     const unsigned own = (unsigned)(gj * I.pitch + gi);
     const gptr<real> Jx = to_global(I.jbase[0]), Jy = to_global(I.jbase[1]);
-    const real jpx = ld(Jx, own * (unsigned)sizeof(real)), jpy = ld(Jy, own * (unsigned)sizeof(real));
     // destination rows and columns of the interior path (periodic wrap only)
     unsigned drow[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
     if (!EDGE) {
@@ -672,8 +674,8 @@ template <typename real, int TX, int TY, bool EDGE, bool WHOLE, bool TRT, bool P
 __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, int src, Patch<real, TX, TY>& S,
                                           QT& Q)
 {
-    real f[9], g[9], h[9];
-    const bool inside = load_patch<real, TX, TY, EDGE, WHOLE>(I, src, S, x0, y0, f, g, h);
+    real f[9], g[9], h[9], jpx = 0, jpy = 0;
+    const bool inside = load_patch<real, TX, TY, EDGE, WHOLE>(I, src, S, x0, y0, f, g, h, jpx, jpy);
     const real* smu = nullptr;
     if constexpr (POT) {
         // uniform branch: every work-item reaches the barriers of fill_mu
@@ -683,7 +685,7 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
     if (!inside) return;
     const int tid = threadIdx.x;
     const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-    node_update<real, TX, TY, EDGE, TRT, POT>(I, S, smu, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h);
+    node_update<real, TX, TY, EDGE, TRT, POT>(I, S, smu, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h, jpx, jpy);
 }
 
 // Interior tiles take the wrap-only path; a whole one needs no per-node
@@ -705,11 +707,13 @@ template <typename real, int TX, int TY>
 __device__ __forceinline__ bool load_any(const Inst<real>& I, const Tile& tl, int src, Patch<real, TX, TY>& S,
                                          real (&f)[9], real (&g)[9], real (&h)[9])
 {
+    real jpx, jpy;  // unused here: the loads are dropped
     if (tl.flags & kTileInterior) {
-        if (tl.flags & kTileWhole) return load_patch<real, TX, TY, false, true>(I, src, S, tl.x0, tl.y0, f, g, h);
-        return load_patch<real, TX, TY, false, false>(I, src, S, tl.x0, tl.y0, f, g, h);
+        if (tl.flags & kTileWhole)
+            return load_patch<real, TX, TY, false, true>(I, src, S, tl.x0, tl.y0, f, g, h, jpx, jpy);
+        return load_patch<real, TX, TY, false, false>(I, src, S, tl.x0, tl.y0, f, g, h, jpx, jpy);
     }
-    return load_patch<real, TX, TY, true, false>(I, src, S, tl.x0, tl.y0, f, g, h);
+    return load_patch<real, TX, TY, true, false>(I, src, S, tl.x0, tl.y0, f, g, h, jpx, jpy);
 }
 
 // Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
