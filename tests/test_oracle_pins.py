@@ -224,6 +224,74 @@ def test_shear_wave_viscosity():
     assert abs(rate / (0.07 * k * k) - 1) < 5e-3
 
 
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def _late_decay_ratio(o, field, axis_coord, kap, steps, offset=0.0):
+    """Ratio of one Fourier mode's amplitude over the last step of a run."""
+    amps = []
+    for _ in range(steps):
+        o.step(1)
+        f = o.fields()[field]
+        line = f[0] if field == "T" else f[:, 0]
+        amps.append(np.sum((line - offset) * np.cos(kap * axis_coord)))
+    return amps[-1] / amps[-2]
+
+
+@pytest.mark.parametrize("rhocp,lam", [(1.0, 0.1), (4.0, 0.3), (2.5, 0.05)])
+def test_thermal_mode_decay_equals_amplification_eigenvalue(rhocp, lam):
+    """Single phase at rest with a uniform heat capacitance k: a Fourier mode
+    of T decays, after the fast non-hydrodynamic modes have died out, by the
+    dominant eigenvalue of the 9x9 amplification matrix of the discrete
+    thermal update of Sec. 3.2: BGK relaxation to w_i T, push streaming
+    (factor exp(-i kappa.c_i)) and the capacitance blend at the destination,
+    A = [E (I - (I - w 1^T)/tau_h) + (k - 1) I] / k.  The matrix is built here
+    from that definition alone; a misplaced k in the blend, a wrong weight or
+    relaxation time changes the eigenvalue."""
+    L = 32
+    kap = 2 * math.pi / L
+    p = single_phase(L, 4, rhocp_l=rhocp, rhocp_h=rhocp, lambda_l=lam, lambda_h=lam)
+    i, _ = wl.grid(L, 4)
+    o = oracle.Oracle(p, fields(np.ones((4, L)), T=1.0 + 1e-3 * np.cos(kap * i)))
+    tau = 0.5 + 3 * lam
+    E = np.diag(np.exp(-1j * kap * CX))
+    A = (E @ (np.eye(9) - (np.eye(9) - np.outer(W9, np.ones(9))) / tau) + (rhocp - 1) * np.eye(9)) / rhocp
+    ev = np.linalg.eigvals(A)
+    lam_max = ev[np.argmax(np.abs(ev))]
+    assert abs(lam_max.imag) < 1e-12
+    r = _late_decay_ratio(o, "T", np.arange(L), kap, 400, offset=1.0)
+    assert abs(r - lam_max.real) <= 1e-9 * (1 - lam_max.real), (r, lam_max)
+    # and the continuum limit lambda kappa^2 / k to second order in kappa
+    assert abs((1 - r) / (lam * kap ** 2 / rhocp) - 1) < 0.05
+
+
+@pytest.mark.parametrize("mu", [0.1, 0.02])
+def test_shear_wave_decay_equals_linearised_eigenvalue(mu):
+    """Single phase, no force: a shear wave u_x = 1e-6 cos(kappa y) decays by
+    the shear eigenvalue of the linearised NS LBE of Sec. 3.1, whose
+    equilibrium is linear in the populations at this amplitude:
+    g_i^eq = 3 p (w_i - delta_i0) + 3 w_i c_i . (sum_j c_j g_j),
+    p = c_s^2/(1 - w_0) sum_{j>0} g_j; A = E (I - (I - Q)/tau_g)."""
+    L = 32
+    kap = 2 * math.pi / L
+    tau = 0.5 + 3 * mu
+    p = single_phase(4, L, mu_l=mu, mu_h=mu)
+    _, j = wl.grid(4, L)
+    z = np.zeros((L, 4))
+    o = oracle.Oracle(p, dict(phi=np.ones((L, 4)), ux=1e-6 * np.cos(kap * j), uy=z, T=z))
+    Q = np.zeros((9, 9))
+    for a in range(9):
+        for b in range(9):
+            Q[a, b] = 3 * (1 / 3) / (1 - W9[0]) * (W9[a] - (a == 0)) * (b != 0) + 3 * W9[a] * (
+                CX[a] * CX[b] + CY[a] * CY[b])
+    A = np.diag(np.exp(-1j * kap * CY)) @ (np.eye(9) - (np.eye(9) - Q) / tau)
+    ev = np.linalg.eigvals(A)
+    nu = mu  # rho = 1
+    lam_sh = ev[np.argmin(np.abs(ev - math.exp(-nu * kap ** 2)))]
+    r = _late_decay_ratio(o, "ux", np.arange(L), kap, 300)
+    assert abs(r - lam_sh.real) <= 1e-8 * (1 - lam_sh.real), (r, lam_sh)
+
+
 def test_grad_T_from_moments():
     """Steady conduction between Dirichlet walls: -sum c_i h_i / (tau_h c_s^2)
     equals the exact temperature gradient (the first-moment relation of the
