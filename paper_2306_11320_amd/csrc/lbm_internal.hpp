@@ -77,8 +77,7 @@ constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4};
 
 // Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
 // `variant` selects the step kernel: 0 BGK only; 1 BGK or two relaxation
-// times per lattice; 2 also the potential form of the capillary force (every
-// tile through the general boundary path).
+// times per lattice; 2 also the potential form of the capillary force.
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
                        int variant, hipStream_t s);
 // Macroscopic fields of level `src`: any output may be null; out_f32 selects
