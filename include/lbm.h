@@ -276,7 +276,9 @@ int lbm_tile_count(void);
 int lbm_tile_shape(int id, int* tx, int* ty);
 /* Selects the tile shape used by subsequent steps; invalidates captured graphs.
  * Tile shapes change only the launch, never the per-node arithmetic.  The
- * default after lbm_init is 64 x 8 (id 3) in FP32 and 64 x 4 (id 0) in FP64. */
+ * default after lbm_init is 64 x 4 (id 0) in FP64; in FP32 it is 64 x 8 (id 3)
+ * when the device holds every 64 x 8 tile of the context's lattices at once,
+ * else 64 x 4. */
 int lbm_set_tile(lbm_ctx* c, int id);
 int lbm_get_tile(const lbm_ctx* c);
 /* Sets how many steps one captured HIP graph holds (0 = plain launches; the

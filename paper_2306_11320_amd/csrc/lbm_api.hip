@@ -298,9 +298,9 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     if (!c) return fail(LBM_EINVAL, "out of host memory");
     c->prec = ps[0].precision;
     c->n = n;
-    // default tile: 64 x 8 in FP32 (fewer ring reloads at 4 waves per SIMD),
-    // 64 x 4 in FP64 (measured fastest for single lattices)
-    c->tile = c->prec == LBM_FP32_DEV ? 3 : 0;
+    // default tile: 64 x 4 (FP64: measured fastest for single lattices; FP32:
+    // see below once the tile tables exist)
+    c->tile = 0;
     c->stream = static_cast<hipStream_t>(stream);
     c->ws = static_cast<char*>(d_ws);
     c->ws_bytes = ws_bytes;
@@ -360,6 +360,18 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
         e = hipMemcpyAsync(c->d_tiles[t], tl.data(), tl.size() * sizeof(lbm::Tile), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return bail(fail(LBM_EHIP, "copy of tile table: %s", hipGetErrorString(e)));
+    }
+    // FP32: 64 x 8 when one round of resident workgroups covers every tile
+    // (fewer ring reloads; 256 x 1024 lattice +1.8%), else 64 x 4 (later rounds
+    // overlap earlier ones; 512 x 2048 lattice +2.3%)
+    if (c->prec == LBM_FP32_DEV) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            lbm::step_occupancy((int)c->prec, 3, c->variant, &per_cu) == hipSuccess && per_cu > 0 && cus > 0)
+            c->tile = c->ntiles[3] <= per_cu * cus ? 3 : 0;
+        else
+            c->tile = 3;
     }
     // equilibrium populations: fields are staged in the lattice's level B
     for (int k = 0; k < n; ++k) {
