@@ -186,6 +186,34 @@ def droplet_table2(rho_ratio: float, nx: int = 160, ny: int = 320, R: float = 20
     return p, f
 
 
+def droplet_finite_ma(Ma: float, nx: int = 160, ny: int = 320, R: float = 20.0) -> tuple[dict, dict]:
+    """The finite-Marangoni runs of Sec. 4.2 at Re = 1: the geometry of
+    ``droplet_table2`` (drop of radius 20 at the centre, |grad T| = 0.1 from
+    T_c = 16 at the bottom wall), equal densities 1, mu = 0.1 and lambda = 0.1
+    in both fluids, sigma_ref = 5e-3, sigma_T = -2.5e-4, and Ma set through the
+    heat capacitance of both fluids: U = -sigma_T |grad T| R / mu = 5e-3,
+    Re = U R / nu = 1, Ma = rho c_p U R / lambda = rho c_p, Ca = 0.1.  The unit
+    normal and grad T come from the stencils (grad_mode 1): with the normal
+    from the moments, a mode seeded by rounding in the bulk grows at Ma >= 10
+    and breaks the drop up after 12-35 R/U, at a time that depends on the
+    rounding."""
+    gradT, Tc = 0.1, 16.0
+    cx, cy = nx / 2.0, ny / 2.0
+    mu, lam, sigma_T = 0.1, 0.1, -2.5e-4
+    U = -sigma_T * gradT * R / mu
+    p = base_params(nx, ny)
+    p.update(bc=[PERIODIC, PERIODIC, WALL_T, WALL_T], W=3.0, grad_mode=1,
+             rho_h=1.0, rho_l=1.0, mu_h=mu, mu_l=mu, lambda_h=lam, lambda_l=lam,
+             rhocp_h=Ma * lam / (U * R), rhocp_l=Ma * lam / (U * R),
+             sigma_ref=5e-3, sigma_T=sigma_T, sigma_TT=0.0, T_ref=Tc + gradT * (cy + 0.5))
+    p["tw_mean"] = [0.0, 0.0, Tc, Tc + gradT * ny]
+    i, j = grid(nx, ny)
+    phi = tanh_profile(np.sqrt((i - cx) ** 2 + (j - cy) ** 2) - R, 3.0)
+    f = dict(phi=phi, ux=np.zeros_like(phi), uy=np.zeros_like(phi), T=Tc + gradT * (j + 0.5))
+    p["meta"] = dict(U=U, R=R, gradT=gradT, Ma=Ma, Re=U * R / mu, Ca=U * mu / 5e-3, cx=cx, cy=cy)
+    return p, f
+
+
 def bubble_positions(nx: int, ny: int, radii=(24.0, 32.0), seed: int = 3):
     rng = np.random.default_rng(seed)
     while True:

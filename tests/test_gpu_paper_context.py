@@ -11,6 +11,12 @@ numbers as context (they come from the authors' runs, not from a closed form).
   1000.  The terminal velocities land within 7 % of the circular-drop (2-D)
   Stokes value U / (2 (1 + mu_r)(1 + lambda_r)) and 7-19 % below Eq. 60, the
   sphere result that Table 2 compares with (paper: 2.4-4.4 % below).
+* Sec. 4.2, finite Marangoni numbers (Ma = 1, 10, 100 at Re = 1, the same
+  drop): the paper shows no numbers (its figure is missing) but states that
+  all cases first accelerate alike, that Ma = 1 settles first, that for
+  Ma >= 10 the velocity falls before it settles, and that the terminal
+  velocity falls with Ma.  With the stencil normal (grad_mode 1): 0.139, 0.124
+  and 0.060 U at t = 30 R/U.
 Bounds: the measured values with margins of 10-25 %.
 
 Parity at these sizes: the unit normal of the Allen-Cahn source is formed in
@@ -130,3 +136,31 @@ def test_high_density_ratio_matches_oracle():
     print(f"U_r oracle {do['u_r']:.6e} GPU {dg['u_r']:.6e}", flush=True)
     assert abs(dg["u_r"] - do["u_r"]) <= 1e-3 * abs(do["u_r"])
     lat.close()
+
+
+def test_finite_marangoni_trends():
+    """Sec. 4.2 at Re = 1, Ma in {1, 10, 100} (heat capacitance 1, 10, 100):
+    the trends the paper states, over 30 R/U (120 000 steps)."""
+    hist = {}
+    for Ma in (1.0, 10.0, 100.0):
+        cfg, f0 = wl.droplet_finite_ma(Ma)
+        announce("finite_marangoni", Ma)
+        U, R = cfg["meta"]["U"], cfg["meta"]["R"]
+        lat = lbm.Lattice(cfg, f0, lbm.FP64)
+        h = []
+        for _ in range(30):
+            lat.step(int(R / U))
+            h.append(lat.diagnostics(raise_unstable=True)["u_r"] / U)
+        lat.close()
+        hist[Ma] = np.array(h)
+        print(f"Ma={Ma}: U_r/U at t = 1, 3, 10, 20, 30 R/U: {h[0]:.4f} {h[2]:.4f} {h[9]:.4f} {h[19]:.4f} "
+              f"{h[29]:.4f}", flush=True)
+    u1, u10, u100 = hist[1.0], hist[10.0], hist[100.0]
+    # the early stage is the same for all
+    assert max(u1[0], u10[0], u100[0]) <= 1.02 * min(u1[0], u10[0], u100[0])
+    # Ma = 1 is steady over the last third
+    assert np.ptp(u1[20:]) <= 0.01 * u1[-1]
+    # Ma >= 10 overshoot and fall
+    assert u10.max() >= 1.04 * u10[-1] and u100.max() >= 1.5 * u100[-1]
+    # terminal velocity falls with Ma
+    assert u1[-1] > u10[-1] > u100[-1]
