@@ -56,8 +56,10 @@ int validate(const lbm_params& p)
     if (p.abi_version != LBM_ABI_VERSION) return fail(LBM_EINVAL, "abi_version %u != %u", p.abi_version, LBM_ABI_VERSION);
     if (p.nx < 3 || p.ny < 3) return fail(LBM_EINVAL, "lattice %ux%u smaller than 3x3", p.nx, p.ny);
     // node offsets within a population plane are 32-bit byte offsets in the kernels
-    if ((uint64_t)(p.nx + 31) / 32 * 32 * p.ny >= (1ull << 28))
-        return fail(LBM_EINVAL, "lattice too large (%ux%u): at most 2^28 nodes", p.nx, p.ny);
+    // node offsets within a level are 32-bit byte offsets in the kernels
+    if ((uint64_t)(p.nx + lbm::kBlock - 1) / lbm::kBlock * lbm::kBlock * p.ny * lbm::kPlanes *
+            (p.precision == LBM_FP64 ? 8 : 4) >= (1ull << 32))
+        return fail(LBM_EINVAL, "lattice too large (%ux%u): a time level must stay below 4 GiB", p.nx, p.ny);
     if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return fail(LBM_EINVAL, "unknown precision %u", p.precision);
     for (int s = 0; s < 4; ++s)
         if (p.bc[s] > LBM_BC_OUTLET) return fail(LBM_EINVAL, "unknown boundary kind %u on side %d", p.bc[s], s);
@@ -85,7 +87,7 @@ Layout make_layout(const lbm_params& p, size_t rsz, size_t& cursor)
     Layout L{};
     L.nx = (int)p.nx;
     L.ny = (int)p.ny;
-    L.pitch = (int)align_up(p.nx, 32);
+    L.pitch = (int)align_up(p.nx, lbm::kBlock);
     L.plane = (long long)align_up((size_t)L.pitch * p.ny, kAlign / rsz);
     const size_t level = (size_t)lbm::kPlanes * L.plane * rsz;
     L.pop_off[0] = cursor;
@@ -111,7 +113,7 @@ lbm::Inst<real> make_inst(const lbm_params& p, const Layout& L, char* ws)
     I.pop[1] = reinterpret_cast<real*>(ws + L.pop_off[1]);
     I.jprev = reinterpret_cast<real*>(ws + L.jprev_off);
     for (int l = 0; l < 2; ++l)
-        for (int q = 0; q < 27; ++q) I.qbase[l][q] = I.pop[l] + (size_t)q * (size_t)L.plane;
+        for (int q = 0; q < 27; ++q) I.qbase[l][q] = I.pop[l] + lbm::pop_index(q, 0);
     I.jbase[0] = I.jprev;
     I.jbase[1] = I.jprev + L.plane;
     I.nx = L.nx;
@@ -596,29 +598,38 @@ int lbm_get_state(lbm_ctx* c, int instance, double* f, double* g, double* h, dou
     const size_t rsz = real_size(c->prec);
     const size_t nn = (size_t)L.nx * L.ny;
     const int lvl = (int)(c->step & 1);
-    std::vector<char> buf((size_t)L.plane * rsz);
-    auto fetch = [&](size_t off, double* dst, double shift_per_w, int k) -> int {
-        HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + off, buf.size(), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t level_b = (size_t)lbm::kPlanes * L.plane * rsz;
+    std::vector<char> lev(level_b), buf((size_t)L.plane * rsz);
+    HIP_TRY(hipMemcpyAsync(lev.data(), c->ws + L.pop_off[lvl], level_b, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // population q (q >= 0) from the level copy, or the plane at byte offset
+    // off (q < 0)
+    auto fetch = [&](int q, size_t off, double* dst, double shift_per_w, int k) -> int {
+        if (q < 0) {
+            HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + off, buf.size(), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+        const char* src = q < 0 ? buf.data() : lev.data();
         const double sh = k >= 0 ? W9[k] * shift_per_w : 0.0;
         for (int j = 0; j < L.ny; ++j)
             for (int i = 0; i < L.nx; ++i) {
-                const size_t s = (size_t)j * L.pitch + i;
-                const double v = rsz == 8 ? reinterpret_cast<const double*>(buf.data())[s]
-                                          : (double)reinterpret_cast<const float*>(buf.data())[s];
+                const size_t n0 = (size_t)j * L.pitch + i;
+                const size_t s = q < 0 ? n0 : (size_t)lbm::pop_index(q, (long long)n0);
+                const double v = rsz == 8 ? reinterpret_cast<const double*>(src)[s]
+                                          : (double)reinterpret_cast<const float*>(src)[s];
                 dst[(size_t)j * L.nx + i] = v + sh;
             }
         return LBM_OK;
     };
     const size_t plane_b = (size_t)L.plane * rsz;
     for (int k = 0; k < 9; ++k) {
-        if (f && (rc = fetch(L.pop_off[lvl] + (lbm::kF + k) * plane_b, f + k * nn, p.phi0_dev, k))) return rc;
-        if (g && (rc = fetch(L.pop_off[lvl] + (lbm::kG + k) * plane_b, g + k * nn, 0.0, k))) return rc;
-        if (h && (rc = fetch(L.pop_off[lvl] + (lbm::kH + k) * plane_b, h + k * nn, p.T0_dev, k))) return rc;
+        if (f && (rc = fetch(lbm::kF + k, 0, f + k * nn, p.phi0_dev, k))) return rc;
+        if (g && (rc = fetch(lbm::kG + k, 0, g + k * nn, 0.0, k))) return rc;
+        if (h && (rc = fetch(lbm::kH + k, 0, h + k * nn, p.T0_dev, k))) return rc;
     }
     if (jprev)
         for (int q = 0; q < 2; ++q)
-            if ((rc = fetch(L.jprev_off + q * plane_b, jprev + q * nn, 0.0, -1))) return rc;
+            if ((rc = fetch(-1, L.jprev_off + q * plane_b, jprev + q * nn, 0.0, -1))) return rc;
     if (step) *step = c->step;
     return LBM_OK;
 }
@@ -644,29 +655,40 @@ int lbm_set_state(lbm_ctx* c, int instance, const double* f, const double* g, co
         HIP_TRY(hipMemcpyAsync(c->ws + L.pop_off[new_lvl], c->ws + L.pop_off[old_lvl], level_b,
                                hipMemcpyDeviceToDevice, c->stream));
     }
-    std::vector<char> buf((size_t)L.plane * rsz, 0);
-    auto put = [&](size_t off, const double* srcp, double shift_per_w, int k) -> int {
+    // the new level on the host (populations not given keep their values)
+    std::vector<char> lev(level_b), buf((size_t)L.plane * rsz, 0);
+    HIP_TRY(hipMemcpyAsync(lev.data(), c->ws + L.pop_off[new_lvl], level_b, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // population q (q >= 0) into the level copy, or the plane at byte offset
+    // off (q < 0, copied at once)
+    auto put = [&](int q, size_t off, const double* srcp, double shift_per_w, int k) -> int {
+        char* dst = q < 0 ? buf.data() : lev.data();
         const double sh = k >= 0 ? W9[k] * shift_per_w : 0.0;
         for (int j = 0; j < L.ny; ++j)
             for (int i = 0; i < L.nx; ++i) {
-                const size_t d = (size_t)j * L.pitch + i;
+                const size_t n0 = (size_t)j * L.pitch + i;
+                const size_t d = q < 0 ? n0 : (size_t)lbm::pop_index(q, (long long)n0);
                 const double v = srcp[(size_t)j * L.nx + i] - sh;
-                if (rsz == 8) reinterpret_cast<double*>(buf.data())[d] = v;
-                else reinterpret_cast<float*>(buf.data())[d] = (float)v;
+                if (rsz == 8) reinterpret_cast<double*>(dst)[d] = v;
+                else reinterpret_cast<float*>(dst)[d] = (float)v;
             }
-        HIP_TRY(hipMemcpyAsync(c->ws + off, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (q < 0) {
+            HIP_TRY(hipMemcpyAsync(c->ws + off, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
         return LBM_OK;
     };
     const size_t plane_b = (size_t)L.plane * rsz;
     for (int k = 0; k < 9; ++k) {
-        if (f && (rc = put(L.pop_off[new_lvl] + (lbm::kF + k) * plane_b, f + k * nn, p.phi0_dev, k))) return rc;
-        if (g && (rc = put(L.pop_off[new_lvl] + (lbm::kG + k) * plane_b, g + k * nn, 0.0, k))) return rc;
-        if (h && (rc = put(L.pop_off[new_lvl] + (lbm::kH + k) * plane_b, h + k * nn, p.T0_dev, k))) return rc;
+        if (f && (rc = put(lbm::kF + k, 0, f + k * nn, p.phi0_dev, k))) return rc;
+        if (g && (rc = put(lbm::kG + k, 0, g + k * nn, 0.0, k))) return rc;
+        if (h && (rc = put(lbm::kH + k, 0, h + k * nn, p.T0_dev, k))) return rc;
     }
+    HIP_TRY(hipMemcpyAsync(c->ws + L.pop_off[new_lvl], lev.data(), level_b, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     if (jprev)
         for (int q = 0; q < 2; ++q)
-            if ((rc = put(L.jprev_off + q * plane_b, jprev + q * nn, 0.0, -1))) return rc;
+            if ((rc = put(-1, L.jprev_off + q * plane_b, jprev + q * nn, 0.0, -1))) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->step = step;
     return LBM_OK;
@@ -707,7 +729,7 @@ int lbm_checkpoint_save(lbm_ctx* c, void* host_buf, size_t bytes)
     for (int k = 0; k < c->n; ++k) {
         const Layout& L = c->lay[k];
         CkptHeader hd{};
-        std::memcpy(hd.magic, "LBMCKPT1", 8);
+        std::memcpy(hd.magic, "LBMCKPT2", 8);
         hd.version = LBM_ABI_VERSION;
         hd.prec = c->prec;
         hd.n = c->n;
@@ -739,7 +761,7 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* host_buf, size_t bytes)
     const size_t rsz = real_size(c->prec);
     CkptHeader first{};
     std::memcpy(&first, p, sizeof(first));
-    if (std::memcmp(first.magic, "LBMCKPT1", 8) || first.hash != hsh || first.prec != c->prec || first.n != c->n)
+    if (std::memcmp(first.magic, "LBMCKPT2", 8) || first.hash != hsh || first.prec != c->prec || first.n != c->n)
         return fail(LBM_EINVAL, "checkpoint was written by a context with different parameters");
     const int lvl = (int)(first.step & 1);
     for (int k = 0; k < c->n; ++k) {

@@ -8,12 +8,20 @@
 
 namespace lbm {
 
-// Population storage of one lattice: 27 planes (f_0..8, g_0..8, h_0..8) per
-// time level, each plane `plane` elements long with rows `pitch` elements
-// apart (x fastest).  Level A/B alternate every step.  f and h are stored as
-// deviations from the rest equilibrium w_i phi0 and w_i T0; g as is.
+// Population storage of one lattice, per time level: nodes are numbered
+// idx = y * pitch + x (x fastest, rows `pitch` nodes apart, pitch a multiple of
+// kBlock) and grouped in blocks of kBlock consecutive nodes; a block holds the
+// 27 populations (f_0..8, g_0..8, h_0..8) as 27 runs of kBlock values.  A level is
+// 27 * `plane` elements.  Levels A/B alternate every step.  f and h are stored
+// as deviations from the rest equilibrium w_i phi0 and w_i T0; g as is.
 constexpr int kPlanes = 27;
+constexpr int kBlock = 64;
 constexpr int kF = 0, kG = 9, kH = 18;
+// Element index, within a level, of population q of node idx.
+__host__ __device__ constexpr long long pop_index(int q, long long idx)
+{
+    return ((idx / kBlock) * kPlanes + q) * kBlock + idx % kBlock;
+}
 
 // Per-lattice constants, in the working precision.  Properties are stored as
 // xi(phi) = xi_a + xi_b * phi (linear interpolation between phi = -1 and +1).
@@ -21,9 +29,9 @@ template <typename real>
 struct Inst {
     real* pop[2];        // time levels A and B
     real* jprev;         // 2 planes: (phi u)_x, (phi u)_y of the previous level
-    // Base of population plane q of each level (pop[l] + q * plane) and of the
-    // two (phi u) planes: the step kernel reads them as uniform values instead
-    // of forming 64-bit products per plane.
+    // Address of population q of node 0 of each level (pop[l] + q * kBlock;
+    // node idx adds its block offset) and the bases of the two (phi u) planes:
+    // the step kernel reads them as uniform values.
     real* qbase[2][27];
     real* jbase[2];
     int nx, ny, pitch, grad_mode;

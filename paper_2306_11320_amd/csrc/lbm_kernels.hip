@@ -60,6 +60,15 @@ __device__ inline gptr<real> dst_plane(const Inst<real>& I, int lev, int q)
 {
     return to_global(I.qbase[lev][q]);
 }
+// Byte offset of node idx from the base of any population of its level: the
+// populations of kBlock consecutive nodes (one row segment) are stored as 27
+// runs of kBlock values, block after block.
+template <typename real>
+__device__ inline unsigned noff(unsigned idx)
+{
+    return ((idx / kBlock) * (unsigned)(kPlanes * kBlock) + (idx % kBlock)) * (unsigned)sizeof(real);
+}
+
 // Element at a 32-bit byte offset from a (uniform) base.
 template <typename T>
 __device__ inline T ld(gptr<const T> base, unsigned off) { return *(gptr<const T>)((gptr<const char>)base + off); }
@@ -189,8 +198,8 @@ __device__ inline void fill_entry(const Inst<real>& I, int src, Patch<real, TX, 
     real sf = 0, sh = 0, hk[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        sf += ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
-        hk[k] = ld(src_plane(I, src, kH + k), idx * (unsigned)sizeof(real));
+        sf += ld(src_plane(I, src, kF + k), noff<real>(idx));
+        hk[k] = ld(src_plane(I, src, kH + k), noff<real>(idx));
         sh += hk[k];
     }
     const real dphi = (EDGE && !rn) ? aphi + sphi * sf : sf;
@@ -245,8 +254,8 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
         const unsigned ridx = (unsigned)(wrap1(y0 + hy, I.ny) * I.pitch + wrap1(x0 + hx, I.nx));
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            rf[k] = ld(src_plane(I, src, kF + k), ridx * (unsigned)sizeof(real));
-            rh[k] = ld(src_plane(I, src, kH + k), ridx * (unsigned)sizeof(real));
+            rf[k] = ld(src_plane(I, src, kF + k), noff<real>(ridx));
+            rh[k] = ld(src_plane(I, src, kH + k), noff<real>(ridx));
         }
     }
     if (inside) {
@@ -254,9 +263,9 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
         real sf = 0, sh = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f[k] = ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
-            h[k] = ld(src_plane(I, src, kH + k), idx * (unsigned)sizeof(real));
-            g[k] = ld(src_plane(I, src, kG + k), idx * (unsigned)sizeof(real));
+            f[k] = ld(src_plane(I, src, kF + k), noff<real>(idx));
+            h[k] = ld(src_plane(I, src, kH + k), noff<real>(idx));
+            g[k] = ld(src_plane(I, src, kG + k), noff<real>(idx));
         }
         // (phi u) of the previous level, needed after the barrier
         jpx = ld(to_global<const real>(I.jbase[0]), idx * (unsigned)sizeof(real));
@@ -309,7 +318,7 @@ __device__ inline real phi_at(const Inst<real>& I, int src, int gx, int gy)
     const unsigned idx = (unsigned)(sy * I.pitch + sx);
     real sf = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) sf += ld(src_plane(I, src, kF + k), idx * (unsigned)sizeof(real));
+    for (int k = 0; k < 9; ++k) sf += ld(src_plane(I, src, kF + k), noff<real>(idx));
     (void)aT; (void)sT;
     return rn ? sf : aphi + sphi * sf;
 }
@@ -629,10 +638,10 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
         else di = drow[cy(k) + 1] + dcol[cx(k) + 1];
         if (in_lattice) {
             const int cd = c + cy(k) * PX + cx(k);
-            st(dst_plane(I, dst, kF + k), di * (unsigned)sizeof(real), (real)(fsk));
-            st(dst_plane(I, dst, kG + k), di * (unsigned)sizeof(real), (real)(gsk));
+            st(dst_plane(I, dst, kF + k), noff<real>(di), (real)(fsk));
+            st(dst_plane(I, dst, kG + k), noff<real>(di), (real)(gsk));
             const real hold = S.h[k][cd];
-            st(dst_plane(I, dst, kH + k), di * (unsigned)sizeof(real), (real)(hold + (hsk - hold) * S.irc[cd]));
+            st(dst_plane(I, dst, kH + k), noff<real>(di), (real)(hold + (hsk - hold) * S.irc[cd]));
         } else if (EDGE) {
             const int kb = opp(k);
             const int bc = I.bc[side];
@@ -660,10 +669,10 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
                 gb = -gsk + real(2) * w * m.rho * (real(4.5) * cu * cu - real(1.5) * q.uu);
                 hb = -hsk + real(2) * w * m.theta;
             }
-            st(dst_plane(I, dst, kF + kb), own * (unsigned)sizeof(real), (real)(fb));
-            st(dst_plane(I, dst, kG + kb), own * (unsigned)sizeof(real), (real)(gb));
+            st(dst_plane(I, dst, kF + kb), noff<real>(own), (real)(fb));
+            st(dst_plane(I, dst, kG + kb), noff<real>(own), (real)(gb));
             const real hold = S.h[kb][c];
-            st(dst_plane(I, dst, kH + kb), own * (unsigned)sizeof(real), (real)(hold + (hb - hold) * S.irc[c]));
+            st(dst_plane(I, dst, kH + kb), noff<real>(own), (real)(hold + (hb - hold) * S.irc[c]));
         }
     }
 }
@@ -847,7 +856,7 @@ __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __res
     const int i = (int)(x % I.nx), j = (int)(x / I.nx);
     const double phi = staged[x], ux = staged[n + x], uy = staged[2 * n + x], T = staged[3 * n + x];
     const gptr<real> __restrict__ A = to_global(I.pop[src]);
-    const long long P = I.plane, idx = (long long)j * I.pitch + i;
+    const long long idx = (long long)j * I.pitch + i;
     if (!shift) {
         const double p = has_p ? staged[4 * n + x] : 0.0;
         const double rho = rho_a + rho_b * phi;
@@ -856,10 +865,10 @@ __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __res
         for (int k = 0; k < 9; ++k) {
             const double w = wgt<double>(k);
             const double cu = cx(k) * ux + cy(k) * uy;
-            A[(kF + k) * P + idx] = (real)(w * ((phi - phi0) + 3.0 * phi * cu));
-            A[(kG + k) * P + idx] =
+            A[pop_index(kF + k, idx)] = (real)(w * ((phi - phi0) + 3.0 * phi * cu));
+            A[pop_index(kG + k, idx)] =
                 (real)(3.0 * p * (w - (k == 0 ? 1.0 : 0.0)) + rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            A[(kH + k) * P + idx] = (real)(w * (T - T0));
+            A[pop_index(kH + k, idx)] = (real)(w * (T - T0));
         }
         return;
     }
@@ -878,9 +887,9 @@ __global__ void k_init(const Inst<real>* __restrict__ insts, const double* __res
         const double dg = 3.0 * (p - pc) * (w - (k == 0 ? 1.0 : 0.0)) +
                           w * (rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - rhoc * (3.0 * cuc + 4.5 * cuc * cuc - 1.5 * uuc));
         const double dh = w * (T - Tc);
-        A[(kF + k) * P + idx] = (real)((double)A[(kF + k) * P + idx] + df);
-        A[(kG + k) * P + idx] = (real)((double)A[(kG + k) * P + idx] + dg);
-        A[(kH + k) * P + idx] = (real)((double)A[(kH + k) * P + idx] + dh);
+        A[pop_index(kF + k, idx)] = (real)((double)A[pop_index(kF + k, idx)] + df);
+        A[pop_index(kG + k, idx)] = (real)((double)A[pop_index(kG + k, idx)] + dg);
+        A[pop_index(kH + k, idx)] = (real)((double)A[pop_index(kH + k, idx)] + dh);
     }
 }
 
