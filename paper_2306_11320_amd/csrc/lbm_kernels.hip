@@ -18,10 +18,12 @@
 //      and blends with the destination's old h_i, both read from LDS.
 // There is no MFMA on this path: it is bound by HBM traffic.
 //
-// Storage is structure-of-arrays planes, x fastest, f and h kept as deviations
-// from w_i phi0 and w_i T0 (exact for BGK, streaming, bounce-back and the
-// blend, whose weights sum to one), g as is.  The bases of the 27 planes of
-// each time level come precomputed in the lattice's parameter block.
+// Storage: nodes x fastest in blocks of 64 consecutive nodes of a row, each
+// block holding the 27 populations as runs of 64 values; f and h kept as
+// deviations from w_i phi0 and w_i T0 (exact for BGK, streaming, bounce-back
+// and the blend, whose weights sum to one), g as is.  The base of each
+// population of each time level comes precomputed in the lattice's parameter
+// block.
 #include "lbm_internal.hpp"
 
 namespace lbm {
@@ -45,11 +47,11 @@ __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
 __device__ inline bool has_direction(float n2) { return n2 >= 1.17549435e-38f; }
 __device__ inline bool has_direction(double n2) { return n2 > 0.0; }
 
-// Node offsets within a population plane are 32-bit (the host checks that a
-// plane holds fewer than 2^29 nodes); the plane base is uniform, so loads and
-// stores take a scalar base and a 32-bit vector offset.
-// Base of population plane q of time level `lev`, read from the lattice's
-// parameter block (a scalar load).
+// Node offsets within a time level are 32-bit byte offsets (the host keeps a
+// level below 4 GiB); the population base is uniform, so loads and stores take
+// a scalar base and a 32-bit vector offset.
+// Base of population q of time level `lev`, read from the lattice's parameter
+// block (a scalar load).
 template <typename real>
 __device__ inline gptr<const real> src_plane(const Inst<real>& I, int lev, int q)
 {
