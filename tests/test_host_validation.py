@@ -1,7 +1,7 @@
 """Host-side parameter validation of the C ABI (no GPU call is made):
 lbm_workspace_bytes returns 0 and lbm_last_error names the cause for every
 parameter set the library rejects, and the workspace size of a valid lattice
-holds the two time levels of 27 population planes."""
+holds the two time levels of the 27 populations."""
 import ctypes as C
 
 import pytest
@@ -64,3 +64,17 @@ def test_rejected_parameters(over, why):
     p = _params(**over)
     assert L.lbm_workspace_bytes(C.byref(p)) == 0
     assert why in L.lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("prec,word", [(lbm.FP32_DEV, 4), (lbm.FP64, 8)])
+def test_lattice_size_limit(prec, word):
+    """One time level (nx rounded up to 64, times ny, times 27 values) must stay
+    below 4 GiB: the kernels address a level with 32-bit byte offsets."""
+    L = _lib()
+    nx = 4096
+    ny_max = (2 ** 32 - 1) // (nx * 27 * word)
+    ok = _params(precision=prec, nx=nx, ny=ny_max)
+    assert L.lbm_workspace_bytes(C.byref(ok)) >= 2 * 27 * nx * ny_max * word
+    bad = _params(precision=prec, nx=nx, ny=ny_max + 1)
+    assert L.lbm_workspace_bytes(C.byref(bad)) == 0
+    assert "4 GiB" in L.lbm_last_error().decode()
