@@ -167,6 +167,9 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  * Synchronizes the stream before returning.
  * Errors: LBM_EINVAL (bad sizes, tau <= 1/2, rhocp <= 0, one periodic side with
  * a non-periodic opposite side, NULL pointers), LBM_ENOSPACE, LBM_EHIP.
+ * A heat capacitance below 1 is accepted (LBM_OK), but lbm_last_error() then
+ * holds a text starting with "warning:": the destination blend of Eq. 28 is a
+ * convex combination of h* and the old h only for rho c_p >= 1.
  */
 int lbm_init(const lbm_params* p, const double* phi0, const double* ux0, const double* uy0,
              const double* T0, void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
@@ -203,8 +206,8 @@ enum { LBM_REINIT_EQUILIBRIUM = 0, LBM_REINIT_SHIFT = 1 };
  * Re-initialises lattice `instance` from caller-owned device fields (nx*ny
  * elements each, x fastest, FP64 if in_dtype is LBM_OUT_F64, FP32 if
  * LBM_OUT_F32) of phi, u, T and the pressure p (d_p may be NULL).
- *   LBM_REINIT_EQUILIBRIUM: populations := the equilibria of Eqs. (9), (17)
- *     and (33) at the given fields (p = 0 if d_p is NULL);
+ *   LBM_REINIT_EQUILIBRIUM: populations := the equilibria f^eq and g^eq of
+ *     Sec. 3.1 and h^eq of Sec. 3.2 at the given fields (p = 0 if d_p is NULL);
  *   LBM_REINIT_SHIFT: populations += eq(given fields) - eq(current fields of
  *     the lattice), so their non-equilibrium part is kept (the current p is
  *     kept if d_p is NULL).

@@ -70,30 +70,69 @@ class Diag(C.Structure):
         return out
 
 
+def _bind(L):
+    """Declares the C signatures of an oracle library handle."""
+    dp = C.POINTER(C.c_double)
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.POINTER(Params), dp, dp, dp, dp]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+    L.orc_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
+    L.orc_macros_all.argtypes = [C.c_void_p, dp]
+    L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, C.POINTER(C.c_int64)]
+    L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp, C.c_int64]
+    L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_step_count_writes.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    L.orc_get_threads.restype = C.c_int
+    assert L.orc_sizeof_params() == C.sizeof(Params), "oracle params layout mismatch"
+    assert L.orc_sizeof_diag() == C.sizeof(Diag), "oracle diag layout mismatch"
+    return L
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
                 build()
-            L = C.CDLL(_LIB)
-            dp = C.POINTER(C.c_double)
-            L.orc_create.restype = C.c_void_p
-            L.orc_create.argtypes = [C.POINTER(Params), dp, dp, dp, dp]
-            L.orc_destroy.argtypes = [C.c_void_p]
-            L.orc_step.argtypes = [C.c_void_p, C.c_int64]
-            L.orc_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
-            L.orc_macros_all.argtypes = [C.c_void_p, dp]
-            L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, C.POINTER(C.c_int64)]
-            L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp, C.c_int64]
-            L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
-            L.orc_set_threads.argtypes = [C.c_int]
-            L.orc_step_count_writes.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
-            L.orc_get_threads.restype = C.c_int
-            assert L.orc_sizeof_params() == C.sizeof(Params), "oracle params layout mismatch"
-            assert L.orc_sizeof_diag() == C.sizeof(Diag), "oracle diag layout mismatch"
-            _lib = L
+            _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def build_variant(source_text: str, out_path: str) -> str:
+    """Compiles an edited copy of the oracle's C source (same flags) into
+    out_path.  Used by the tests that plant a mistake in the oracle to show
+    that its pins catch it; the product never calls this."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(source_text)
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-std=c99", "-w", src, "-o", out_path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+class use_library:
+    """Context manager: Oracle objects created inside it run the library at
+    `path` (an oracle variant built by build_variant)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        lib()
+        with _lock:
+            self._saved = _lib
+            _lib = _bind(C.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        with _lock:
+            _lib = self._saved
+        return False
 
 
 def _dp(a: np.ndarray):

@@ -5,6 +5,7 @@
 #include "lbm.h"
 #include "lbm_internal.hpp"
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -55,9 +56,10 @@ int validate(const lbm_params& p)
 {
     if (p.abi_version != LBM_ABI_VERSION) return fail(LBM_EINVAL, "abi_version %u != %u", p.abi_version, LBM_ABI_VERSION);
     if (p.nx < 3 || p.ny < 3) return fail(LBM_EINVAL, "lattice %ux%u smaller than 3x3", p.nx, p.ny);
-    // node offsets within a population plane are 32-bit byte offsets in the kernels
+    if (p.nx > (uint32_t)INT_MAX || p.ny > (uint32_t)INT_MAX)
+        return fail(LBM_EINVAL, "lattice %ux%u: sizes must fit a signed 32-bit integer", p.nx, p.ny);
     // node offsets within a level are 32-bit byte offsets in the kernels
-    if ((uint64_t)(p.nx + lbm::kBlock - 1) / lbm::kBlock * lbm::kBlock * p.ny * lbm::kPlanes *
+    if (((uint64_t)p.nx + lbm::kBlock - 1) / lbm::kBlock * lbm::kBlock * p.ny * lbm::kPlanes *
             (p.precision == LBM_FP64 ? 8 : 4) >= (1ull << 32))
         return fail(LBM_EINVAL, "lattice too large (%ux%u): a time level must stay below 4 GiB", p.nx, p.ny);
     if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return fail(LBM_EINVAL, "unknown precision %u", p.precision);
@@ -79,6 +81,12 @@ int validate(const lbm_params& p)
     if (!(p.rhocp_l > 0 && p.rhocp_h > 0)) return fail(LBM_EINVAL, "heat capacitances must be positive");
     if (!(p.mobility > 0)) return fail(LBM_EINVAL, "mobility must be positive (tau_phi > 1/2)");
     if (!(p.W > 0)) return fail(LBM_EINVAL, "interface width must be positive");
+    // The destination blend of Eq. 28, h_i <- [h*_i + (rho c_p - 1) h_i] / rho c_p,
+    // is a convex combination only for rho c_p >= 1: accepted, with a warning
+    // left in the thread's message text.
+    if (p.rhocp_l < 1.0 || p.rhocp_h < 1.0)
+        (void)fail(LBM_OK, "warning: heat capacitance below 1 (%g, %g): the blend of Eq. 28 is not convex",
+                   p.rhocp_l, p.rhocp_h);
     return LBM_OK;
 }
 

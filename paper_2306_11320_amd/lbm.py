@@ -358,12 +358,19 @@ class Lattice:
         """Chooses the tile shape (and the persistent grid of a batched lattice)
         by timing each candidate on the live state (trial steps are ordinary
         steps).  With ``cache`` (a JSON file), a choice stored for the same
-        precision and lattice sizes is reused instead of timing again."""
+        precision, kernel variant, kernel source and lattice sizes is reused
+        instead of timing again."""
+        import hashlib
         import json
-        key = f"p{self.precision}:" + ",".join(f"{nx}x{ny}" for ny, nx in self.shapes)
+        # the step kernel instantiated for these lattices: BGK only, two
+        # relaxation times somewhere, or the potential force form somewhere
+        variant = 2 if any(int(c.get("force_form", 0)) == 1 for c in self.cfgs) else (
+            1 if any(int(c.get("collision", 0)) == 1 for c in self.cfgs) else 0)
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "lbm_kernels.hip"), "rb") as fh:
+            src = hashlib.sha256(fh.read()).hexdigest()[:12]
+        key = f"p{self.precision}:v{variant}:k{src}:" + ",".join(f"{nx}x{ny}" for ny, nx in self.shapes)
         if len(key) > 200:
-            import hashlib
-            key = f"p{self.precision}:n{self.n}:" + hashlib.sha1(key.encode()).hexdigest()[:16]
+            key = f"p{self.precision}:v{variant}:k{src}:n{self.n}:" + hashlib.sha1(key.encode()).hexdigest()[:16]
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as fh:

@@ -220,7 +220,7 @@ def _device(fields, dtype="float64"):
 
 def test_reinit_equilibrium_with_pressure():
     """An equilibrium restart at given (phi, u, T, p) writes the equilibria of
-    the three LBEs (Eqs. 9, 17, 33) and the moments give the fields back
+    the three LBEs (f^eq, g^eq of Sec. 3.1, h^eq of Sec. 3.2) and the moments give the fields back
     (uniform phi, no gravity: no force term in the velocity)."""
     announce("reinit_equilibrium")
     cfg, f0 = wl.tiny(64, 40, seed=5)
@@ -298,7 +298,7 @@ def test_fp32_dev_full_bubbles():
 
 
 def test_sweep_full_batch_sampled():
-    """The 64-lattice sweep (9.79 M nodes) in the launch configuration the
+    """The 64-lattice sweep (10.43 M nodes) in the launch configuration the
     benchmark times (one batched launch per step, autotuned tile and grid):
     three lattices sampled across the batch against the FP64 oracle run alone."""
     items = wl.sweep(64, seed=4)

@@ -78,3 +78,26 @@ def test_lattice_size_limit(prec, word):
     bad = _params(precision=prec, nx=nx, ny=ny_max + 1)
     assert L.lbm_workspace_bytes(C.byref(bad)) == 0
     assert "4 GiB" in L.lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("nx", [2 ** 32 - 10, 2 ** 31])
+def test_huge_width_rejected(nx):
+    """Widths near 2^32 (which would wrap when rounded up to whole 64-node
+    blocks in 32-bit arithmetic) and widths beyond a signed 32-bit integer are
+    rejected, not accepted as a small lattice."""
+    L = _lib()
+    p = _params(nx=nx, ny=3)
+    assert L.lbm_workspace_bytes(C.byref(p)) == 0
+    assert "signed 32-bit" in L.lbm_last_error().decode()
+
+
+def test_heat_capacitance_below_one_warns():
+    """rho c_p < 1 is accepted (the blend of Eq. 28 is then not a convex
+    combination): the workspace is sized and the message text holds a warning."""
+    L = _lib()
+    ok = _params(rhocp_l=1.0, rhocp_h=2.0)
+    assert L.lbm_workspace_bytes(C.byref(ok)) > 0
+    p = _params(rhocp_l=0.5, rhocp_h=2.0)
+    assert L.lbm_workspace_bytes(C.byref(p)) > 0
+    msg = L.lbm_last_error().decode()
+    assert msg.startswith("warning:") and "heat capacitance" in msg

@@ -114,3 +114,53 @@ def test_adam_matches_closed_form_first_step():
     g = np.array([0.3, -2.0, 1e-3])
     p, _, _ = cr.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-12)
     assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-6)
+
+
+def check_adam_constant_gradient(adam, steps=40):
+    """Under a constant gradient the bias-corrected moments equal g and g^2 at
+    every step, so each step moves a weight by lr * sign(g) (up to eps): after
+    t steps the weight has moved t * lr * sign(g)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    lr = 0.01
+    p, m1, m2 = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, steps + 1):
+        p, m1, m2 = adam(p, g, m1, m2, t, lr=lr, eps=1e-12)
+        assert np.allclose(p, -lr * t * np.sign(g), rtol=1e-6, atol=0), t
+
+
+def check_adam_impulse_response(adam, steps=30, b1=0.9, b2=0.999):
+    """A single gradient g at step 1 and none afterwards: the moments decay
+    geometrically, m_t = b1^(t-1) (1 - b1) g and v_t = b2^(t-1) (1 - b2) g^2, so
+    step t moves a weight by lr m_t/(1 - b1^t) / (sqrt(v_t/(1 - b2^t)) + eps)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    lr, eps = 0.01, 1e-12
+    p, m1, m2 = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, steps + 1):
+        gt = g if t == 1 else np.zeros(3)
+        q, m1, m2 = adam(p, gt, m1, m2, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        mt = b1 ** (t - 1) * (1 - b1) * g
+        vt = b2 ** (t - 1) * (1 - b2) * g * g
+        want = -lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(q - p, want, rtol=1e-9, atol=0), t
+        p = q
+
+
+def test_adam_constant_gradient():
+    check_adam_constant_gradient(cr.adam)
+
+
+def test_adam_impulse_response():
+    check_adam_impulse_response(cr.adam)
+
+
+def test_adam_scale_invariant():
+    """Adam's step does not depend on the scale of the gradients (up to eps)."""
+    rng = np.random.default_rng(3)
+    gs = rng.standard_normal((12, 5))
+    out = []
+    for s in (1.0, 1e3):
+        p, m1, m2 = np.zeros(5), np.zeros(5), np.zeros(5)
+        for t, g in enumerate(gs, start=1):
+            p, m1, m2 = cr.adam(p, s * g, m1, m2, t, lr=0.01, eps=1e-14)
+        out.append(p)
+    assert np.allclose(out[0], out[1], rtol=1e-9, atol=0)
