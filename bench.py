@@ -1,18 +1,25 @@
 """Throughput of the fused lattice Boltzmann step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload droplet|bubbles|channel|sweep] [--no-cpu]
-                    [--surrogate N] [--potential]
+    python bench.py [--steps K] [--warmup W] [--workload sweep|bubbles|droplet|channel]
+                    [--precision fp32|fp64] [--only] [--no-cpu] [--surrogate N] [--potential]
 
-A step is one time step of the three coupled D2Q9 LBEs over the whole lattice
-(one fused kernel launch).  The default workload is the droplet-migration
-lattice, 256 x 1024 nodes, Ma = 1, density/viscosity/conductivity/heat-
-capacitance ratio 0.5, timed in FP32 deviation storage (the headline value)
-and in FP64.  With the droplet workload the learned surrogate is also timed
-against the plain FP32 lattice update on N fresh 256 x 1024 droplet lattices
-(sweep parameters, seed 55) over 10 blocks of 100 steps after 30000 steps of
-warm-up, with its errors.  Prints one JSON line.
-
-Only one GPU is used; --gpus above 1 is refused.
+A step is one time step of the three coupled D2Q9 LBEs over every node of the
+workload (one fused kernel launch).  The headline workload is the largest
+single-GPU configuration: 64 droplet-migration lattices of uneven size
+(NX in 128..256, NY = 4 NX, 10.43 M nodes, 2.3 GB of populations) advanced
+together by one persistent launch per step in FP32 deviation storage, tiles
+chosen by the autotuner.  The same JSON line also carries:
+* the batched launch against the same 64 lattices advanced one after another;
+* the two-bubble channel of Sec. 4.3 (512 x 2048) in FP64 (470 MB, streamed
+  from HBM) and FP32 (235 MB, at the edge of the 256 MB Infinity Cache);
+* the 256 x 1024 droplet (cache-resident: 59 MB FP32, 117 MB FP64);
+* for each timed workload the error against the FP64 oracle after a 200-step
+  window from the initial state (three lattices of the sweep);
+* the learned surrogate against the plain FP32 lattice update;
+* the oracle on the host cores, all cores and one thread.
+Working-set bytes are reported next to every number.  --only times just the
+named workload and precision (profiling runs).  Only one GPU is used; --gpus
+above 1 is refused.
 """
 from __future__ import annotations
 
@@ -31,6 +38,12 @@ METRIC = "MLUPS (3 coupled D2Q9 LBEs) FP64 vs FP32; surrogate speedup at ≤1% L
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2306_11320_amd", "csrc", "lbm_kernels.hip")
+WORKLOADS = {"sweep": "batched_droplet_sweep_64", "bubbles": "two_bubbles_512x2048",
+             "droplet": "droplet_migration_256x1024", "channel": "heated_channel_64x32"}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -55,17 +68,17 @@ def make_workload(name: str):
     from paper_2306_11320_amd import workloads as wl
     if name == "droplet":
         cfg, f0 = wl.droplet(Ma=1.0, ratio=0.5)
-        return [(cfg, f0)], dict(workload="droplet_migration_256x1024", nx=256, ny=1024, Ma=1.0, ratio=0.5)
+        return [(cfg, f0)], dict(workload=WORKLOADS[name], nx=256, ny=1024, Ma=1.0, ratio=0.5)
     if name == "bubbles":
         cfg, f0 = wl.two_bubbles(sigma_TT=0.2)
-        return [(cfg, f0)], dict(workload="two_bubbles_512x2048", nx=512, ny=2048, sigma_TT=0.2)
+        return [(cfg, f0)], dict(workload=WORKLOADS[name], nx=512, ny=2048, sigma_TT=0.2)
     if name == "channel":
         cfg, f0 = wl.heated_channel(2.0)
-        return [(cfg, f0)], dict(workload="heated_channel_64x32", nx=64, ny=32, lambda_ratio=2.0)
+        return [(cfg, f0)], dict(workload=WORKLOADS[name], nx=64, ny=32, lambda_ratio=2.0)
     if name == "sweep":
         items = wl.sweep(64, seed=4)
         nodes = sum(c["nx"] * c["ny"] for c, _ in items)
-        return items, dict(workload="batched_droplet_sweep_64", instances=64, nodes=nodes)
+        return items, dict(workload=WORKLOADS[name], instances=64, nodes=nodes, seed=4)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -81,7 +94,10 @@ def prewarm(seconds: float = 0.3):
         torch.cuda.synchronize()
 
 
-def time_gpu(items, prec, steps, warmup, tile=None, autotune=False):
+def time_gpu(items, prec, steps, warmup, tile=None, autotune=False, tune_cache=None):
+    """Times `steps` steps after `warmup` untimed ones.  The events are
+    recorded on the lattice's own stream, which every step kernel runs on, so
+    their interval is the step kernels' time."""
     import torch
     from paper_2306_11320_amd import lbm
     if len(items) == 1:
@@ -92,7 +108,7 @@ def time_gpu(items, prec, steps, warmup, tile=None, autotune=False):
     if tile is not None:
         lat.set_tile(tile)
     elif autotune:
-        tuned = lat.autotune(steps_per_trial=max(2, min(50, warmup // 20 or 2)))
+        tuned = lat.autotune(steps_per_trial=max(2, min(50, warmup // 20 or 2)), cache=tune_cache)
     lat.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -110,6 +126,34 @@ def time_gpu(items, prec, steps, warmup, tile=None, autotune=False):
     lat.close()
     return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes, tuned=tuned, tile=tile_used,
                 mlups=nodes * steps / (ms * 1e-3) / 1e6, finite=d["n_nonfinite"] == 0, max_u=d["max_u"])
+
+
+def lbm_leg(name, prec_name, steps, warmup, tile=None, potential=False, tune_cache=None):
+    """MLUPS and the roofline of the step kernel for one workload and precision."""
+    from paper_2306_11320_amd import lbm
+    items, desc = make_workload(name)
+    if potential:
+        for cfg, _ in items:
+            cfg["force_form"] = lbm.FORCE_POTENTIAL
+        desc["force_form"] = "potential"
+    prec = lbm.FP32_DEV if prec_name == "fp32" else lbm.FP64
+    log(f"{desc['workload']}: {prec_name}, {steps} steps")
+    r = time_gpu(items, prec, steps, warmup, tile, autotune=len(items) > 1 and tile is None, tune_cache=tune_cache)
+    if not r["finite"]:
+        raise SystemExit(f"{desc['workload']} {prec_name}: non-finite state after the timed steps")
+    word = 4 if prec_name == "fp32" else 8
+    per_launch = lbm.bytes_per_update(prec) * r["nodes"]
+    achieved = per_launch / (r["ms_per_step"] * 1e-3) / 1e9
+    out = {"workload": desc["workload"], "value": round(r["mlups"], 1), "unit": "MLUPS",
+           "ms_per_step": round(r["ms_per_step"], 5), "precision": "fp32_deviation" if word == 4 else "fp64",
+           "tile": r["tile"], "nodes": r["nodes"], "working_set_bytes": (2 * 27 + 2) * word * r["nodes"],
+           "algorithmic_bytes_per_launch": per_launch,
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None if potential else stored_traffic(name, prec_name)}}
+    if r["tuned"] is not None:
+        out["autotuned"] = r["tuned"]
+    return out, items, desc
 
 
 def time_sequential(items, prec, steps, warmup):
@@ -132,24 +176,79 @@ def time_sequential(items, prec, steps, warmup):
     return total_ms / steps
 
 
-def cpu_baseline(items, budget_s: float = 15.0):
-    """The FP64 oracle as it stands on the host cores, on the first lattice of
-    the workload: steps are added until about budget_s of CPU work."""
+def _field_errors(got: dict, ref: dict, T0: float) -> dict:
+    """Relative L2 of phi and of T - T0, and the rms error of u over max |u|."""
+    import numpy as np
+    out = {}
+    for k in ("phi", "T"):
+        a, b = got[k], ref[k]
+        if k == "T":
+            a, b = a - T0, b - T0
+        out[k] = float(np.sqrt(np.sum((a - b) ** 2) / max(np.sum(b ** 2), 1e-300)))
+    umax = max(float(np.abs(ref["ux"]).max()), float(np.abs(ref["uy"]).max()), 1e-300)
+    for k in ("ux", "uy"):
+        out[k] = float(np.sqrt(np.mean((got[k] - ref[k]) ** 2)) / umax)
+    return out
+
+
+def oracle_error(name: str, prec_name: str, steps: int = 200, lattices=(0, 1, 2)):
+    """The GPU path against the FP64 oracle on the timed workload: both take
+    `steps` steps from the initial state (for the sweep, lattices `lattices`
+    of the batch, stepped inside the batch), then the fields are compared."""
+    import oracle
+    from paper_2306_11320_amd import lbm
+    items, _ = make_workload(name)
+    prec = lbm.FP32_DEV if prec_name == "fp32" else lbm.FP64
+    if len(items) > 1:
+        lat = lbm.Lattice.batch(items, prec)
+        which = list(lattices)
+    else:
+        lat = lbm.Lattice(items[0][0], items[0][1], prec)
+        which = [0]
+    lat.step(steps)
+    worst = {}
+    for k in which:
+        cfg, f0 = items[k]
+        o = oracle.Oracle(cfg, f0)
+        o.step(steps)
+        e = _field_errors(lat.fields(k), o.fields(), float(cfg.get("T_ref", 0.0)))
+        worst = {q: max(worst.get(q, 0.0), v) for q, v in e.items()}
+    lat.close()
+    return {"steps": steps, "lattices": which if len(items) > 1 else None,
+            "rel_l2": {k: float(f"{v:.3e}") for k, v in worst.items()}}
+
+
+def cpu_baseline(items, budget_s: float = 12.0):
+    """The FP64 oracle as it stands, on the first lattice of the workload from
+    its initial state: steps are added until about budget_s of CPU work, once
+    on every host core (OpenMP) and once on one thread."""
     import oracle
     cfg, f0 = items[0]
-    o = oracle.Oracle(cfg, f0)
-    threads = oracle.Oracle.threads()
-    t0 = time.perf_counter()
-    o.step(2)
-    dt = time.perf_counter() - t0
-    n = max(2, int(budget_s / max(dt / 2, 1e-6)))
-    t0 = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t0
     nodes = cfg["nx"] * cfg["ny"]
-    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"{cfg['nx']}x{cfg['ny']} lattice of the workload, {n} FP64 steps from the initial state, "
-                       f"{dt:.1f} s on {threads} OpenMP threads")
+
+    def run(threads):
+        o = oracle.Oracle(cfg, f0, threads=threads)
+        used = oracle.Oracle.threads()
+        t0 = time.perf_counter()
+        o.step(2)
+        dt = time.perf_counter() - t0
+        n = max(2, int(budget_s / max(dt / 2, 1e-6)))
+        t0 = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t0
+        return nodes * n / dt / 1e6, used, n, dt
+
+    # OpenMP's default thread count (OMP_NUM_THREADS where set): the host
+    # cores this process may use
+    all_cores = oracle.Oracle.threads()
+    va, ca, na, da = run(all_cores)
+    v1, c1, n1, d1 = run(1)
+    oracle.Oracle(cfg, f0, threads=all_cores)
+    sample = f"{cfg['nx']}x{cfg['ny']} lattice of the workload (lattice 0), FP64 steps from the initial state"
+    return dict(value=round(va, 2), unit="MLUPS", cores=ca, kind="oracle",
+                sample=f"{sample}: {na} steps in {da:.1f} s on {ca} OpenMP threads",
+                single_thread={"value": round(v1, 2), "unit": "MLUPS", "cores": c1,
+                               "sample": f"{sample}: {n1} steps in {d1:.1f} s on one thread"})
 
 
 def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000):
@@ -187,12 +286,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2048)
     ap.add_argument("--warmup", type=int, default=256)
-    ap.add_argument("--workload", default="droplet")
+    ap.add_argument("--workload", default="sweep", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--only", action="store_true", help="time only --workload in --precision")
     ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="reuse (or store) the autotuner's choice for a batch in this file")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--no-error", action="store_true", help="skip the oracle error windows")
     ap.add_argument("--surrogate", type=int, default=4, metavar="N",
-                    help="lattices for the surrogate leg (droplet workload only; 0 skips it)")
+                    help="lattices for the surrogate leg (0 skips it)")
     ap.add_argument("--potential", action="store_true",
                     help="potential form of the capillary force (-phi grad mu_phi) instead of Eq. 11's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -225,55 +328,49 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": ms,
                           "copy_GBps": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
         return
-    items, cfgdesc = make_workload(args.workload)
-    if args.potential:
-        for cfg, _ in items:
-            cfg["force_form"] = lbm.FORCE_POTENTIAL
-        cfgdesc["force_form"] = "potential"
     prewarm()
-    print(f"[bench] workload {cfgdesc['workload']}: FP32 deviation storage, {args.steps} steps", file=sys.stderr,
-          flush=True)
-    r32 = time_gpu(items, lbm.FP32_DEV, args.steps, args.warmup, args.tile, autotune=len(items) > 1)
-    bpl = lbm.bytes_per_update(lbm.FP32_DEV) * r32["nodes"]
-    achieved = bpl / (r32["ms_per_step"] * 1e-3) / 1e9
-    # the stored counters cover the kernel of the paper's force form
-    traffic = None if args.potential else stored_traffic(args.workload, "fp32")
+    head, items, desc = lbm_leg(args.workload, args.precision, args.steps, args.warmup, args.tile, args.potential,
+                                args.tune_cache)
+    cfg_out = dict(desc, precision=head["precision"], parallelism="single_gpu", tile=head["tile"],
+                   working_set_bytes=head["working_set_bytes"],
+                   algorithmic_bytes_per_launch=head["algorithmic_bytes_per_launch"])
+    if "autotuned" in head:
+        cfg_out["autotuned"] = head["autotuned"]
     out = {
-        "metric": METRIC, "value": round(r32["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": dict(cfgdesc, precision="fp32_deviation", parallelism="single_gpu", tile=r32["tile"]),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "metric": METRIC, "value": head["value"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic", "config": cfg_out,
+        "roofline": head["roofline"],
     }
-    ws = (2 * 27 + 2) * 4 * r32["nodes"]
-    out["config"]["working_set_bytes"] = ws
-    out["config"]["algorithmic_bytes_per_launch"] = bpl
-    if len(items) > 1:
-        print("[bench] sequential single-lattice baseline", file=sys.stderr, flush=True)
-        seq_ms = time_sequential(items, lbm.FP32_DEV, max(16, args.steps // 8), max(4, args.warmup // 8))
-        out["batched"] = {"tuned": r32["tuned"], "sequential_ms_per_step": round(seq_ms, 5),
-                          "batched_ms_per_step": round(r32["ms_per_step"], 5),
-                          "speedup_over_sequential": round(seq_ms / r32["ms_per_step"], 3)}
-        args.fp32_only = True
-    if not args.fp32_only:
-        print("[bench] FP64", file=sys.stderr, flush=True)
-        r64 = time_gpu(items, lbm.FP64, args.steps, args.warmup, args.tile)
-        b64 = lbm.bytes_per_update(lbm.FP64) * r64["nodes"]
-        a64 = b64 / (r64["ms_per_step"] * 1e-3) / 1e9
-        out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
-                       "tile": r64["tile"],
-                       "working_set_bytes": (2 * 27 + 2) * 8 * r64["nodes"],
-                       "roofline": {"bound": "hbm", "achieved": round(a64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                    "frac": round(a64 / HBM_PEAK_GBS, 4),
-                                    "traffic": None if args.potential
-                                    else stored_traffic(args.workload, "fp64")}}
-    if args.workload == "droplet" and args.surrogate > 0:
-        print("[bench] surrogate", file=sys.stderr, flush=True)
-        out["surrogate"] = surrogate_leg(args.surrogate)
+    if not args.only:
+        if len(items) > 1:
+            log("sequential single-lattice baseline of the batch")
+            seq_ms = time_sequential(items, lbm.FP32_DEV if args.precision == "fp32" else lbm.FP64,
+                                     max(16, args.steps // 8), max(4, args.warmup // 8))
+            out["batched"] = {"sequential_ms_per_step": round(seq_ms, 5),
+                              "batched_ms_per_step": head["ms_per_step"],
+                              "speedup_over_sequential": round(seq_ms / head["ms_per_step"], 3),
+                              "error": "bitwise equal to the sequential runs (tested)"}
+        extra = []
+        for name, prec in (("bubbles", "fp64"), ("bubbles", "fp32"), ("droplet", "fp32"), ("droplet", "fp64")):
+            if (name, prec) != (args.workload, args.precision):
+                extra.append((name, prec))
+        out["other_workloads"] = []
+        for name, prec in extra:
+            leg, _, _ = lbm_leg(name, prec, args.steps, args.warmup, None, args.potential)
+            leg["cache_resident"] = leg["working_set_bytes"] <= 256 * 2 ** 20
+            out["other_workloads"].append(leg)
+        if not args.no_error:
+            log("errors against the FP64 oracle (200-step windows)")
+            out["oracle_error"] = {f"{args.workload}_{args.precision}": oracle_error(args.workload, args.precision)}
+            for name, prec in (("bubbles", "fp64"), ("bubbles", "fp32")):
+                out["oracle_error"][f"{name}_{prec}"] = oracle_error(name, prec)
+        if args.surrogate > 0:
+            log("surrogate")
+            out["surrogate"] = surrogate_leg(args.surrogate)
     if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(items)
     print(json.dumps(out), flush=True)
 

@@ -24,10 +24,18 @@ the bulk too, where its defining vector (the moment vector, or grad phi) is at
 rounding level, so its direction there is set by rounding; the oracle and the
 GPU round differently (contracted multiply-adds), and the difference, scaled by
 the small counter term (1 - phi^2)/(sqrt2 W), grows slowly.  The checks are
-therefore one-step agreement of the populations (g and h to 1e-13 of their
-scale, f to 1e-6 absolute: the bulk counter term is ~1e-5 here) and agreement
-of the fields after many steps to 1e-4 (1e-3 at density ratio 1000; relative
-L2, u against its maximum).
+therefore:
+* one step from the oracle's state after three steps, node by node: g and h
+  to 1e-13 of their scale; f to 2e-13 of its
+  scale wherever every node that pushes into it has a normal fixed beyond
+  rounding, and elsewhere to the validity bound of the counter term,
+  2 (1 - 1/(2 tau_phi)) max_i(w_i |c_i|) lambda_c = (2/9)(1 - 1/(2 tau_phi))
+  lambda_c of the pushing node (two unit vectors differ by at most 2).  A
+  node's normal counts as fixed when a perturbation of 1e-15 in its defining
+  vector (about ten roundings of the populations it is summed from) moves the
+  counter term by less than 1e-14;
+* the fields after many steps to 1e-4 (1e-3 at density ratio 1000; relative
+  L2, u against its maximum), where the bulk differences have spread.
 """
 import numpy as np
 import pytest
@@ -49,13 +57,65 @@ def rel_l2(a, b):
     return float(np.sqrt(np.sum((np.asarray(a) - np.asarray(b)) ** 2) / np.sum(np.asarray(b) ** 2)))
 
 
-def _one_step(o, lat):
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+EPS_V = 1e-15      # perturbation of the vector that defines the unit normal
+FIXED = 1e-14      # counter-term change below which a node's normal is fixed
+
+
+def _normal_allowance(o, cfg):
+    """Per node of the next level: the bound on |f_gpu - f_oracle| that comes
+    from pushing nodes whose unit normal is set by rounding (0 where every
+    pushing node's normal is fixed), and the count of such pushing nodes."""
+    st, M = o.get_state(), o.macros_all()
+    phi = M["phi"]
+    fac = 1.0 - 0.5 / (0.5 + 3.0 * cfg["mobility"])
+    lamc = np.abs(1.0 - phi ** 2) / (np.sqrt(2.0) * cfg["W"])
+    if int(cfg.get("grad_mode", 0)) == 0:
+        jx, jy = phi * M["ux"], phi * M["uy"]
+        f = st["f"]
+        vx = np.tensordot(CX, f, axes=(0, 0)) - jx + 0.5 * (jx - st["jprev"][0])
+        vy = np.tensordot(CY, f, axes=(0, 0)) - jy + 0.5 * (jy - st["jprev"][1])
+    else:
+        vx, vy = M["dphix"], M["dphiy"]
+    vn = np.hypot(vx, vy)
+    full = (2.0 / 9.0) * fac * lamc
+    shift = full * np.minimum(1.0, EPS_V / np.maximum(vn, 1e-300))
+    loose = shift > FIXED
+    allow = np.where(loose, full, 0.0)
+    # a population of node y was pushed by a node of its 3 x 3 neighbourhood
+    # (or bounced back at y itself)
+    pad = np.pad(allow, 1, mode="wrap")
+    ny, nx = allow.shape
+    near = np.max([pad[1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx] for dy in (-1, 0, 1) for dx in (-1, 0, 1)], axis=0)
+    return near, int(loose.sum())
+
+
+def _one_step(cfg, f0, warm=3):
+    """One step from the same state: an oracle takes `warm` steps (from the
+    equilibrium start the moment vector is ~0 everywhere, so every normal
+    would be set by rounding), a GPU lattice receives its exact state, and
+    both take one step."""
+    o = oracle.Oracle(cfg, f0)
+    lat = lbm.Lattice(cfg, f0, lbm.FP64)
+    o.step(warm)
+    st = o.get_state()
+    lat.set_state(0, st["f"], st["g"], st["h"], st["jprev"], st["step"])
+    allow, n_loose = _normal_allowance(o, cfg)
     o.step(1)
     lat.step(1)
     so, sg = o.get_state(), lat.get_state(0)
     for k in ("g", "h"):
         assert np.abs(sg[k] - so[k]).max() <= 1e-13 * np.abs(so[k]).max(), k
-    assert np.abs(sg["f"] - so["f"]).max() <= 1e-6
+    err = np.abs(sg["f"] - so["f"])
+    tight = 2e-13 * np.abs(so["f"]).max()
+    fixed = allow == 0.0
+    print(f"[one step] normals set by rounding at {n_loose} of {allow.size} nodes; f error "
+          f"{err[:, fixed].max():.2e} where fixed (bound {tight:.1e}), "
+          f"{(err[:, ~fixed].max() if (~fixed).any() else 0.0):.2e} elsewhere", flush=True)
+    assert fixed.sum() > 0.3 * allow.size
+    assert (err <= tight + allow[None]).all(), float((err - allow[None]).max())
+    lat.close()
 
 
 def _fields_close(o, lat, tol):
@@ -73,9 +133,9 @@ def test_table1_size_matches_oracle():
     announce("table1_vs_oracle")
     o = oracle.Oracle(cfg, f0)
     lat = lbm.Lattice(cfg, f0, lbm.FP64)
-    _one_step(o, lat)
-    o.step(1999)
-    lat.step(1999)
+    _one_step(cfg, f0)
+    o.step(2000)
+    lat.step(2000)
     _fields_close(o, lat, 1e-4)
     lat.close()
 
@@ -128,9 +188,9 @@ def test_high_density_ratio_matches_oracle():
     announce("rho1000_vs_oracle")
     o = oracle.Oracle(cfg, f0)
     lat = lbm.Lattice(cfg, f0, lbm.FP64)
-    _one_step(o, lat)
-    o.step(499)
-    lat.step(499)
+    _one_step(cfg, f0)
+    o.step(500)
+    lat.step(500)
     _fields_close(o, lat, 1e-3)
     do, dg = o.diagnostics(), lat.diagnostics()
     print(f"U_r oracle {do['u_r']:.6e} GPU {dg['u_r']:.6e}", flush=True)
