@@ -98,6 +98,22 @@ int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int group
 int sur_judge(const float* const* d_a, const float* const* d_b, int h, int w, const sur_scales* scales,
               double* d_part, int groups, double* d_out, void* stream);
 
+/* sur_judge without a scratch argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same kernels and the same result as sur_judge with
+ * `groups` partials.  The partials live in a library-owned static device array
+ * of SUR_JUDGE_MAX_GROUPS * 8 doubles (64 KiB) on each GPU the call runs on,
+ * held until the process ends; the call itself allocates nothing.  `stream`
+ * must belong to the current device.  Every partial it reads is written first
+ * by the same call, so nothing needs clearing, but all calls on one GPU share
+ * the array: two calls that overlap in time on one GPU (different streams or
+ * threads) race; calls ordered on one stream do not.
+ * Errors: -1 with a message if groups is outside [1, SUR_JUDGE_MAX_GROUPS] or
+ * an argument is invalid; -3 if a HIP call fails. */
+#define SUR_JUDGE_MAX_GROUPS 1024
+int sur_judge_noscratch(const float* const* d_a, const float* const* d_b, int h, int w, const sur_scales* scales,
+                        int groups, double* d_out, void* stream);
+
 const char* sur_last_error(void);
 
 #ifdef __cplusplus

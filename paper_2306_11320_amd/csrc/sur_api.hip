@@ -3,6 +3,8 @@
 #include "surrogate.h"
 #include "sur_internal.hpp"
 
+static_assert(SUR_JUDGE_MAX_GROUPS == sur::kJudgeMaxGroups, "judge scratch size");
+
 #include <cstdio>
 #include <string>
 
@@ -161,6 +163,25 @@ int sur_judge(const float* const* d_a, const float* const* d_b, int h, int w, co
     return check(sur::frame_sums(a, &b, (long long)h * w, w, sc, d_part, groups, d_out,
                                  static_cast<hipStream_t>(stream)),
                  "sur_judge");
+}
+
+int sur_judge_noscratch(const float* const* d_a, const float* const* d_b, int h, int w, const sur_scales* scales,
+                        int groups, double* d_out, void* stream)
+{
+    sur::State5 a, b;
+    sur::Scales sc;
+    if (!get_state(d_a, a) || !get_state(d_b, b) || !get_scales(scales, sc) || !d_out || h < 1 || w < 1)
+        return bad("sur_judge_noscratch: bad arguments");
+    if (groups < 1 || groups > SUR_JUDGE_MAX_GROUPS) {
+        char msg[128];
+        snprintf(msg, sizeof(msg), "sur_judge_noscratch: groups %d outside [1, %d]", groups, SUR_JUDGE_MAX_GROUPS);
+        return bad(msg);
+    }
+    double* part = nullptr;
+    int rc = check(sur::judge_scratch_ptr(&part), "sur_judge_noscratch: address of the static scratch");
+    if (rc) return rc;
+    return check(sur::frame_sums(a, &b, (long long)h * w, w, sc, part, groups, d_out, static_cast<hipStream_t>(stream)),
+                 "sur_judge_noscratch");
 }
 
 const char* sur_last_error(void) { return g_err.c_str(); }

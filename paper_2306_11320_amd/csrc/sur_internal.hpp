@@ -35,4 +35,12 @@ hipError_t advance(const float* delta, long long npix, const Scales& sc, const S
 hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,
                       int groups, double* out, hipStream_t s);
 
+// Largest partial-sum count of the allocation-free judge, and the devices it
+// keeps an address for.
+constexpr int kJudgeMaxGroups = 1024;
+constexpr int kMaxDevices = 64;
+// Device address of the current device's judge scratch (kJudgeMaxGroups * 8
+// doubles), looked up on the first call on each device.
+hipError_t judge_scratch_ptr(double** out);
+
 }  // namespace sur

@@ -17,6 +17,7 @@
 // A[l % 32][8 (l / 32) + j] and B[8 (l / 32) + j][l % 32], j = 0..7; the
 // accumulator element i of lane l is C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
 #include "sur_internal.hpp"
+#include <mutex>
 
 namespace sur {
 
@@ -472,6 +473,36 @@ hipError_t advance(const float* delta, long long npix, const Scales& sc, const S
 {
     hipLaunchKernelGGL(k_advance, pix_grid(npix), dim3(256), 0, s, delta, npix, sc, f);
     return hipGetLastError();
+}
+
+// Partial sums of the judge for callers that cannot allocate device memory:
+// a file-scope array of kJudgeMaxGroups * 8 doubles per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address is taken once per device with
+// hipGetSymbolAddress (the device current at that call) and only that address
+// is passed to kernels.
+static __device__ __align__(256) double scratch[kJudgeMaxGroups * 8];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t judge_scratch_ptr(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,

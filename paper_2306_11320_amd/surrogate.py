@@ -76,6 +76,7 @@ def lib():
         L.sur_advance.argtypes = [vp, i64, sp, pp, vp]
         L.sur_light_volume.argtypes = [vp, ip, ip, vp, ip, vp, vp]
         L.sur_judge.argtypes = [pp, pp, ip, ip, sp, vp, ip, vp, vp]
+        L.sur_judge_noscratch.argtypes = [pp, pp, ip, ip, sp, ip, vp, vp]
         L.sur_last_error.restype = C.c_char_p
         _sur = L
     return _sur
@@ -152,6 +153,11 @@ def sur_light_volume(phi, part, out, stream):
 def sur_judge(a, b, sc: SurScales, part, out, stream):
     h, w = a["phi"].shape
     _ck(lib().sur_judge(_state(a), _state(b), h, w, C.byref(sc), _p(part), part.numel() // 8, _p(out), _s(stream)))
+
+
+def sur_judge_noscratch(a, b, sc: SurScales, groups, out, stream):
+    h, w = a["phi"].shape
+    _ck(lib().sur_judge_noscratch(_state(a), _state(b), h, w, C.byref(sc), int(groups), _p(out), _s(stream)))
 
 
 # ---- scaling of a lattice's state -----------------------------------------
