@@ -14,7 +14,8 @@
  *   activations  NHWC, element (n, y, x, c) at ((n*H + y)*W + x)*C + c, with
  *                C = 32 (network input: C = 8), BF16;
  *   weights      [co = 32][tap = 9][ci], tap = 3*(dy+1) + (dx+1), BF16;
- *   W            a multiple of 32; pointers 16-byte aligned.
+ *   W            any width >= 1 (a row is covered by 32-pixel segments; the
+ *                last one is masked); pointers 16-byte aligned.
  */
 #ifndef SURROGATE_H
 #define SURROGATE_H

@@ -34,7 +34,7 @@ int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias,
 {
     if (!d_in || !d_w || !d_out) return bad("sur_conv3x3: NULL tensor");
     if (cin != 8 && cin != 32) return bad("sur_conv3x3: cin must be 8 or 32");
-    if (n < 1 || h < 1 || w < 32 || w % 32) return bad("sur_conv3x3: need n, h >= 1 and w a multiple of 32");
+    if (n < 1 || h < 1 || w < 1) return bad("sur_conv3x3: need n, h, w >= 1");
     if (dil < 1 || dil > w) return bad("sur_conv3x3: need 1 <= dil <= w");
     if (!aligned16(d_in) || !aligned16(d_w)) return bad("sur_conv3x3: in and w must be 16-byte aligned");
     return check(sur::conv(static_cast<const bf16*>(d_in), cin, static_cast<const bf16*>(d_w), d_bias, d_res,
@@ -59,7 +59,7 @@ int sur_weight_grad(const void* d_dy, const void* d_in, int cin, int relu_in, in
 {
     if (!d_dy || !d_in || !d_part || !d_out) return bad("sur_weight_grad: NULL tensor");
     if (cin != 8 && cin != 32) return bad("sur_weight_grad: cin must be 8 or 32");
-    if (n < 1 || h < 1 || w < 32 || w % 32 || groups < 1) return bad("sur_weight_grad: bad sizes");
+    if (n < 1 || h < 1 || w < 1 || groups < 1) return bad("sur_weight_grad: bad sizes");
     if (dil < 1 || dil > w) return bad("sur_weight_grad: need 1 <= dil <= w");
     return check(sur::wgrad(static_cast<const bf16*>(d_dy), static_cast<const bf16*>(d_in), cin, relu_in, dil, n, h, w,
                             d_part, groups, d_out, static_cast<hipStream_t>(stream)),

@@ -44,6 +44,8 @@ __device__ inline float to_f(bf16 v) { return (float)v; }
 // FP32 if OUTF32, else BF16.  Per 32-pixel segment all K / 16 input operands
 // are loaded before the first matrix-core op (rows outside the frame load a
 // clamped row and are zeroed), so the loads of a wave are in flight together.
+// A row of W pixels takes ceil(W / 32) segments; in the last one the pixels
+// beyond the row repeat its last pixel and are not stored.
 template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
 __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                               const float* __restrict__ bias, const void* __restrict__ res,
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
 {
     constexpr int K = 9 * CIN, NKB = (K + 15) / 16;
     const int lane = threadIdx.x % 64;
-    const int segs_per_row = W / 32;
+    const int segs_per_row = (W + 31) / 32;
     const long long nseg = (long long)N * H * segs_per_row;
     const long long wave0 = (long long)blockIdx.x * 4 + threadIdx.x / 64;
     const long long nwaves = (long long)gridDim.x * 4;
@@ -77,6 +79,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
         const int x0 = (int)(seg % segs_per_row) * 32;
         const long long ny = seg / segs_per_row;
         const int y = (int)(ny % H), n = (int)(ny / H);
+        const int xm = x0 + m < W ? x0 + m : W - 1;
         bf16x8 a[NKB];
 #pragma unroll
         for (int q = 0; q < NKB; ++q) {
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
             const int kc = kv ? kk : 0;
             const int tap = kc / CIN, ci = kc % CIN;
             const int yy = y + (tap / 3 - 1) * dil;
-            int xx = x0 + m + (tap % 3 - 1) * dil;  // |offset| <= W, so one wrap suffices
+            int xx = xm + (tap % 3 - 1) * dil;  // |offset| <= W, so one wrap suffices
             xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
             const bool ok = kv && yy >= 0 && yy < H;
             const int yc = ok ? yy : y;
@@ -100,6 +103,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int px = x0 + 8 * (i / 4) + 4 * kh + (i % 4);
+            if (px >= W) continue;
             const long long idx = (row + px) * 32 + co;
             float v = acc[i] + bv;
             if (MASK) v = to_f(mask[idx]) > 0.f ? v : 0.f;
@@ -129,6 +133,7 @@ __global__ void k_adjoint_weights(const bf16* __restrict__ w, int cin, bf16* __r
 // dy[p][co] * A(p + d off(tap))[ci], kk = tap * cin + ci, A = relu(in) if
 // relu_in, dilation d.  Each workgroup walks whole 32-pixel segments; LDS
 // holds dy of the segment and the nine shifted 32-pixel input windows it meets.
+// Pixels of a row's last segment beyond the row contribute zero.
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, const bf16* __restrict__ in, int cin,
                                                int relu_in, int dil, int N, int H, int W, float* __restrict__ part,
                                                int ntiles_n)
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, cons
     __shared__ bf16 sdy[32][33];          // [pixel][co] (+1 pad)
     __shared__ bf16 sa[9][32][33];        // [tap][pixel][ci] (+1 pad), cin <= 32
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int segs_per_row = W / 32;
+    const int segs_per_row = (W + 31) / 32;
     const long long nseg = (long long)N * H * segs_per_row;
     const long long s0 = (long long)blockIdx.x * nseg / gridDim.x, s1 = (long long)(blockIdx.x + 1) * nseg / gridDim.x;
     const int K = 9 * cin;
@@ -148,15 +153,15 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dy, cons
         __syncthreads();
         for (int q = threadIdx.x; q < 32 * 32; q += 256) {
             const int p = q / 32, c = q % 32;
-            sdy[p][c] = dy[(((long long)n * H + y) * W + x0 + p) * 32 + c];
+            sdy[p][c] = x0 + p < W ? dy[(((long long)n * H + y) * W + x0 + p) * 32 + c] : (bf16)0.f;
         }
         for (int q = threadIdx.x; q < 9 * 32 * 32; q += 256) {
             const int c = q % 32, p = (q / 32) % 32, tap = q / (32 * 32);
             const int yy = y + (tap / 3 - 1) * dil;
-            int xx = x0 + p + (tap % 3 - 1) * dil;
+            int xx = (x0 + p < W ? x0 + p : W - 1) + (tap % 3 - 1) * dil;
             xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
             bf16 v = (bf16)0.f;
-            if (c < cin && yy >= 0 && yy < H) {
+            if (c < cin && yy >= 0 && yy < H && x0 + p < W) {
                 v = in[(((long long)n * H + yy) * W + xx) * cin + c];
                 if (relu_in && !(to_f(v) > 0.f)) v = (bf16)0.f;
             }
@@ -377,7 +382,7 @@ static void conv_t(const bf16* in, const bf16* w, const float* bias, const void*
 {
     // a resident grid (6 waves per SIMD on 256 CUs) walks the segments, so
     // each workgroup stages the weights once
-    const long long segs = (long long)N * H * (W / 32);
+    const long long segs = (long long)N * H * ((W + 31) / 32);
     long long groups = (segs + 3) / 4;
     if (groups > 1536) groups = 1536;
     hipLaunchKernelGGL((k_conv<CIN, RELU, OUTF32, RES, MASK>), dim3((unsigned)groups), dim3(256), 0, s, in, w, bias, res,
