@@ -389,6 +389,100 @@ def generate_pairs(items, K: int, starts, device="cuda:0"):
     return X, Y
 
 
+def generate_pairs_uneven(items, K: int, starts, device="cuda:0"):
+    """As generate_pairs for lattices of any sizes (one batched launch per
+    step): returns per-lattice lists Xs[l] (BF16 [S, H_l, W_l, 8]) and Ys[l]
+    (FP32 [S, H_l, W_l, N_OUT]), S = len(starts)."""
+    import torch
+    lat = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    n = len(items)
+    S = len(starts)
+    Xs = [torch.empty((S, ny, nx, 8), dtype=torch.bfloat16, device=device) for ny, nx in lat.shapes]
+    Ys = [torch.empty((S, ny, nx, N_OUT), dtype=torch.float32, device=device) for ny, nx in lat.shapes]
+    sc = [scales_of(c) for c, _ in items]
+    st = lat.stream
+    f0 = [{k: torch.empty(shp, device=device) for k in FIELDS} for shp in lat.shapes]
+    f1 = [{k: torch.empty(shp, device=device) for k in FIELDS} for shp in lat.shapes]
+    t = 0
+    for q, s in enumerate(sorted(starts)):
+        if s < t:
+            raise ValueError("start times must be at least K apart")
+        lat.step(s - t)
+        for k in range(n):
+            lat.fields(k, out="f32", into=f0[k])
+            sur_pack(f0[k], sc[k], Xs[k][q], st)
+        lat.step(K)
+        t = s + K
+        for k in range(n):
+            lat.fields(k, out="f32", into=f1[k])
+            sur_pack_target(f0[k], f1[k], sc[k], Ys[k][q], st)
+    st.synchronize()
+    lat.close()
+    return Xs, Ys
+
+
+def dataset_kappa_uneven(Xs, frac=(0.001, 0.01, 0.01, 0.003, 0.01)) -> tuple:
+    """dataset_kappa over frames of several sizes (mean squares weighted by
+    pixel count)."""
+    import torch
+    tot = sum(x[..., 0].numel() for x in Xs)
+
+    def ms(f):
+        return sum(float(torch.sum(f(x).float() ** 2).item()) for x in Xs) / tot
+    k_u = math.sqrt(0.5 * (ms(lambda x: x[..., 1]) + ms(lambda x: x[..., 2])))
+    rms = (math.sqrt(ms(lambda x: x[..., 0].float() - 1.0)), k_u, k_u, math.sqrt(ms(lambda x: x[..., 3])),
+           math.sqrt(ms(lambda x: x[..., 6].float() + 0.5 * (1.0 - x[..., 0].float()))))
+    return tuple(f * v for f, v in zip(frac, rms))
+
+
+def train_streamed(net: "Surrogate", batches, K: int, starts, iters_per_batch: int, frames: int,
+                   crop_rows: int, lr: float = 1e-3, seed: int = 5, log=print, on_batch=None) -> list:
+    """Trains on lattice trajectories generated batch by batch and discarded
+    after use: for each batch of lattice items (any sizes), the batched FP32
+    lattice update produces the pairs of every start time, then
+    `iters_per_batch` Adam steps each take `frames` pairs of one randomly
+    chosen lattice of the batch (one frame size per step), cut to a random
+    band of `crop_rows` rows at full width (frames are periodic in x).  The
+    learning rate decays by a cosine over all steps.  The network's kappa is
+    set from the first batch.  Returns the loss history."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    total = iters_per_batch * len(batches)
+    hist, it = [], 0
+    for bi, items in enumerate(batches):
+        t0 = time.perf_counter()
+        Xs, Ys = generate_pairs_uneven(items, K, starts, device=net.device)
+        if bi == 0 and net.kappa == KAPPA_UNIT:
+            net.kappa = dataset_kappa_uneven(Xs)
+        for Y in Ys:
+            for c in range(N_OUT):
+                Y[..., c] /= net.kappa[c]
+        t_gen = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        S = len(starts)
+        for _ in range(iters_per_batch):
+            li = int(torch.randint(0, len(Xs), (1,), generator=g))
+            X, Y = Xs[li], Ys[li]
+            idx = torch.randint(0, S, (frames,), generator=g).to(X.device)
+            xb, yb = X.index_select(0, idx), Y.index_select(0, idx)
+            H = X.shape[1]
+            if crop_rows < H:
+                y0 = int(torch.randint(0, H - crop_rows + 1, (1,), generator=g))
+                xb, yb = xb[:, y0:y0 + crop_rows], yb[:, y0:y0 + crop_rows]
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / max(1, total)))
+            hist.append(net.train_step(xb.contiguous(), yb.contiguous(), lr_t))
+            it += 1
+        torch.cuda.synchronize(net.device)
+        t_train = time.perf_counter() - t0
+        if log:
+            log(f"[stream] batch {bi + 1}/{len(batches)}: {len(items)} lattices, {len(items) * S} pairs generated in "
+                f"{t_gen:.1f} s, {iters_per_batch} steps in {t_train:.1f} s, loss {np.mean(hist[-iters_per_batch:]):.3e}")
+        if on_batch:
+            on_batch(bi, hist)
+        del Xs, Ys
+    return hist
+
+
 def dataset_kappa(X, frac=(0.001, 0.01, 0.01, 0.003, 0.01)) -> tuple:
     """kappa_c = frac_c x the rms deviation from rest of field c over the
     inputs X (scaled units: phi - 1, u / U, (T - T_rest) / dT, p / P).  phi
@@ -442,19 +536,23 @@ class Hybrid:
     state (a shift restart: the populations' non-equilibrium part is kept, the
     equilibria move to the network's fields, pressure included) beside the
     network's own prediction of that block, and compares the two (relative L2
-    on deviations from rest).  The trigger uses phi and T: right after a
-    restart the lattice's velocity carries a capillary transient (the network's
-    small phi errors change the interface's chemical potential), so its
-    one-block velocity is no measure of the network's.  The velocity error is
-    recorded all the same.  An error above `tol_check`, or a light-phase volume
-    drift above `tol_vol` since the start, hands the following
-    `fallback_blocks` blocks to the lattice update, which continues from its
-    judged result; otherwise the network's state continues."""
+    on deviations from rest).  phi and T trigger above `tol_check`.  Right
+    after a restart the lattice's velocity carries a capillary transient (the
+    network's small phi errors change the interface's chemical potential), so
+    the judged velocity error overstates the network's own (measured: 0.9-2.1 %
+    judged where the velocity is 0.5-1.0 % off the plain lattice update); the
+    velocity triggers above `tol_check_u`, set above that transient.  A
+    trigger, or a light-phase volume drift above `tol_vol` since the start,
+    hands the following `fallback_blocks` blocks to the lattice update, which
+    continues from its judged result; otherwise the network's state
+    continues."""
 
     TRIGGER = (0, 3)            # phi, T
+    TRIGGER_U = (1, 2)          # ux, uy
 
     def __init__(self, net: Surrogate, lat, cfg: dict, K: int = 100, check_every: int = 10,
-                 tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None):
+                 tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None,
+                 tol_check_u: float = 0.03):
         import torch
         if net.stream is not lat.stream:
             raise ValueError("the network must run on the lattice's stream")
@@ -463,6 +561,7 @@ class Hybrid:
         self.net, self.lat, self.K = net, lat, int(K)
         self.C = int(check_every)
         self.tol_check, self.tol_vol = float(tol_check), float(tol_vol)
+        self.tol_check_u = float(tol_check_u)
         self.fallback_blocks = self.C if fallback_blocks is None else int(fallback_blocks)
         self.sc = scales_of(cfg, net.kappa)
         ny, nx = lat.shapes[0]
@@ -528,10 +627,11 @@ class Hybrid:
                 vols = self.vol[:n_net].cpu().numpy()
                 drift = float(np.max(np.abs(vols - self.vol0)) / self.vol0)
             trig = max(err[c] for c in self.TRIGGER)
+            trig_u = max(err[c] for c in self.TRIGGER_U)
             self.stats["max_judge"] = max(self.stats["max_judge"], trig)
-            self.stats["max_judge_u"] = max(self.stats["max_judge_u"], err[1], err[2])
+            self.stats["max_judge_u"] = max(self.stats["max_judge_u"], trig_u)
             self.stats["max_drift"] = max(self.stats["max_drift"], drift)
-            if not (trig <= self.tol_check and drift <= self.tol_vol):      # NaN fails too
+            if not (trig <= self.tol_check and trig_u <= self.tol_check_u and drift <= self.tol_vol):  # NaN fails
                 self.stats["fallbacks"] += 1
                 fallback_left = self.fallback_blocks
                 self.s, self.s_lbm = self.s_lbm, self.s

@@ -259,11 +259,12 @@ def two_bubbles(sigma_TT: float = 0.2, nx: int = 512, ny: int = 2048, radii=(24.
 # Batched parameter sweep of droplet migrations of uneven lattice size
 # ---------------------------------------------------------------------------
 
-def sweep(n: int = 64, seed: int = 4, nx_range=(128, 256)) -> list[tuple[dict, dict]]:
+def sweep(n: int = 64, seed: int = 4, nx_range=(128, 256), laplace_p: bool = False) -> list[tuple[dict, dict]]:
     """n droplet-migration instances: NX uniform in nx_range, NY = 4 NX, drop at
     (NX/2, NY/4) with R uniform in [16, 40], Ma uniform in [0.1, 50], lambda_r
     uniform in [0.5, 2], rho = 1, mu = 0.05, lambda_h = 0.5 in both phases,
-    rho c_p = 20 Ma in both phases."""
+    rho c_p = 20 Ma in both phases.  laplace_p: start with the Young-Laplace
+    pressure (see sweep_instance)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
@@ -272,7 +273,7 @@ def sweep(n: int = 64, seed: int = 4, nx_range=(128, 256)) -> list[tuple[dict, d
         R = float(rng.uniform(16.0, 40.0))
         Ma = float(rng.uniform(0.1, 50.0))
         lr = float(rng.uniform(0.5, 2.0))
-        out.append(sweep_instance(nx, ny, R, Ma, lr))
+        out.append(sweep_instance(nx, ny, R, Ma, lr, laplace_p=laplace_p))
     return out
 
 

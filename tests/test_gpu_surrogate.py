@@ -57,10 +57,12 @@ def stream():
 
 @pytest.mark.parametrize("cin", [8, 32])
 @pytest.mark.parametrize("relu_in", [False, True])
-@pytest.mark.parametrize("dil,W", [(1, 64), (3, 64), (1, 256), (3, 256), (16, 256), (2, 128)])
+@pytest.mark.parametrize("dil,W", [(1, 64), (3, 64), (1, 256), (3, 256), (16, 256), (2, 128),
+                                   (1, 129), (3, 200), (16, 41), (1, 7)])
 def test_conv_forward(cin, relu_in, dil, W, stream):
     """Frame widths of one to eight 32-pixel segments per row (periodic wrap at
-    both ends of the row) and dilations up to 16."""
+    both ends of the row), ragged widths whose last segment is partly outside
+    the row, and dilations up to 16."""
     rng = np.random.default_rng(cin + relu_in + 10 * dil + W)
     N, H = 2, 5
     announce("conv_forward", cin, relu_in, dil, W)
@@ -90,7 +92,8 @@ def test_adjoint_input_gradient(stream):
     rng = np.random.default_rng(7)
     N, H = 1, 6
     announce("adjoint")
-    for cin, dil, W in ((8, 1, 32), (32, 1, 32), (32, 2, 32), (8, 5, 32), (32, 4, 128), (8, 16, 256)):
+    for cin, dil, W in ((8, 1, 32), (32, 1, 32), (32, 2, 32), (8, 5, 32), (32, 4, 128), (8, 16, 256), (32, 3, 200),
+                        (8, 2, 45)):
         w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, cin)))
         g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
         wt = torch.empty((32, 9, 32), dtype=torch.bfloat16, device="cuda")
@@ -108,10 +111,11 @@ def test_adjoint_input_gradient(stream):
 
 @pytest.mark.parametrize("cin", [8, 32])
 @pytest.mark.parametrize("dil", [1, 4])
-def test_weight_and_bias_gradient(cin, dil, stream):
-    rng = np.random.default_rng(11 + cin + dil)
-    N, H, W = 2, 7, 96
-    announce("wgrad", cin, dil)
+@pytest.mark.parametrize("W", [96, 129])
+def test_weight_and_bias_gradient(cin, dil, W, stream):
+    rng = np.random.default_rng(11 + cin + dil + W)
+    N, H = 2, 7
+    announce("wgrad", cin, dil, W)
     a = cr.bf16_round(rng.standard_normal((N, H, W, cin)))
     g = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
     for relu_in in (False, True):
@@ -308,7 +312,7 @@ def test_hybrid_bookkeeping():
         assert torch.equal(h.s[k], fr[k]), k
     lat2 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
     net.stream = lat2.stream
-    h2 = sur.Hybrid(net, lat2, cfg, K=100, check_every=4, tol_check=1e9, tol_vol=1e9)
+    h2 = sur.Hybrid(net, lat2, cfg, K=100, check_every=4, tol_check=1e9, tol_vol=1e9, tol_check_u=1e9)
     st2 = h2.run(8)
     assert (st2["net_blocks"], st2["lbm_blocks"], st2["fallbacks"], st2["judged"]) == (6, 2, 0, 2)
     lat3 = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
