@@ -251,14 +251,19 @@ def cpu_baseline(items, budget_s: float = 12.0):
                                "sample": f"{sample}: {n1} steps in {d1:.1f} s on one thread"})
 
 
-def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000):
-    """Hybrid rollout of the trained surrogate against the plain FP32 lattice
-    update: speedup and relative L2 errors over `blocks` blocks of 100 steps."""
+def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000, weights: str = "surrogate_k100.npz",
+                  lattices: str = "256x1024"):
+    """Hybrid rollout of a trained surrogate against the plain FP32 lattice
+    update: speedup and relative L2 errors over `blocks` blocks of 100 steps,
+    on fresh 256 x 1024 droplet lattices drawn with the sweep's parameters
+    (lattices="256x1024") or on lattices of the batched-sweep generator
+    (lattices="sweep", uneven sizes); seed 55 for both."""
     from paper_2306_11320_amd import surrogate as S
+    from paper_2306_11320_amd import workloads as wl
     from paper_2306_11320_amd.train_surrogate import sweep_items
-    wpath = os.path.join(ROOT, "paper_2306_11320_amd", "weights", "surrogate_k100.npz")
+    wpath = os.path.join(ROOT, "paper_2306_11320_amd", "weights", weights)
     net = S.Surrogate.load(wpath)
-    items = sweep_items(n, 55, 256, 1024)
+    items = sweep_items(n, 55, 256, 1024) if lattices == "256x1024" else wl.sweep(n, seed=55, laplace_p=True)
     res = S.evaluate(net, items, warm=warm, blocks=blocks, K=100, check_every=10, chunk=blocks,
                      log=lambda m: print(m, file=sys.stderr, flush=True))
     sp = [sum(r["t_ref_ms"]) / sum(r["t_hybrid_ms"]) for r in res]
@@ -266,8 +271,9 @@ def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000):
     ok = [s_ for s_, e in zip(sp, err) if e <= 0.01]
     srt = sorted(ok)
     return {
-        "workload": "droplet_sweep_256x1024", "K": 100, "blocks": blocks, "warm_steps": warm,
-        "instances": n, "weights": "paper_2306_11320_amd/weights/surrogate_k100.npz",
+        "workload": "droplet_sweep_256x1024" if lattices == "256x1024" else "batched_sweep_generator_uneven",
+        "K": 100, "blocks": blocks, "warm_steps": warm,
+        "instances": n, "weights": f"paper_2306_11320_amd/weights/{weights}",
         "speedup": [round(v, 3) for v in sp],
         "max_rel_l2": [round(v, 5) for v in err],
         "max_rel_l2_net_only": [round(max(r["err_net_only"][-1].values()), 5) for r in res],
@@ -296,6 +302,8 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the oracle error windows")
     ap.add_argument("--surrogate", type=int, default=4, metavar="N",
                     help="lattices for the surrogate leg (0 skips it)")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate leg on --surrogate lattices (profiling runs)")
     ap.add_argument("--potential", action="store_true",
                     help="potential form of the capillary force (-phi grad mu_phi) instead of Eq. 11's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -329,6 +337,9 @@ def main():
                           "copy_GBps": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
         return
     prewarm()
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_leg(max(1, args.surrogate))}), flush=True)
+        return
     head, items, desc = lbm_leg(args.workload, args.precision, args.steps, args.warmup, args.tile, args.potential,
                                 args.tune_cache)
     cfg_out = dict(desc, precision=head["precision"], parallelism="single_gpu", tile=head["tile"],
@@ -369,6 +380,9 @@ def main():
         if args.surrogate > 0:
             log("surrogate")
             out["surrogate"] = surrogate_leg(args.surrogate)
+            log("surrogate trained on 2000 trajectories of the batched-sweep generator")
+            out["surrogate_sweep2000"] = surrogate_leg(2, warm=22000, weights="surrogate_k100_sweep2000.npz",
+                                                       lattices="sweep")
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(items)
