@@ -128,6 +128,14 @@ class NetRef:
         gd = np.zeros_like(delta)
         gd[..., :nout] = 2.0 * e * scale
         gd = bf16_round(gd)
+        gW, gb = self.grads_from(x, hs, gd)
+        return loss, gW, gb, delta
+
+    def grads_from(self, x, hs, gd):
+        """The backward pass alone: weight and bias gradients from the
+        network input x, the stored activations h0..h4 and the BF16 gradient
+        gd of the loss with respect to delta (all as given)."""
+        x = bf16_round(x)
         gW = [None] * 6
         gb = [None] * 6
         d = self.d
@@ -140,4 +148,4 @@ class NetRef:
             gh = bf16_round(gh + conv_input_grad(gh, self.W[r], d[r]) * (hs[r - 1] > 0))
         gW[0] = conv_weight_grad(gh, x, d[0])
         gb[0] = gh.sum(axis=(0, 1, 2))
-        return loss, gW, gb, delta
+        return gW, gb

@@ -140,6 +140,17 @@ def test_table1_size_matches_oracle():
     lat.close()
 
 
+@pytest.mark.parametrize("lambda_r", [0.2, 1.0])
+def test_table1_size_paper_normal_one_step(lambda_r):
+    """The heated channel at Table 1's size with the paper-literal unit normal
+    (from the moments of f, Sec. 3.1) instead of the stencil normal its
+    long runs use: one step from the oracle's state, node by node."""
+    cfg, f0 = wl.heated_channel_table1(lambda_r)
+    cfg["grad_mode"] = 0
+    announce("table1_paper_normal_one_step", lambda_r)
+    _one_step(cfg, f0)
+
+
 @pytest.mark.parametrize("lambda_r,bounds", [(1.0, dict(T=2.5e-4, ux=0.16, uy=0.13)),
                                              (0.2, dict(T=1.2e-2, ux=0.21, uy=0.18))])
 def test_table1_context(lambda_r, bounds):
