@@ -88,8 +88,9 @@ enum { LBM_OUT_F64 = 0, LBM_OUT_F32 = 1 };
 typedef struct lbm_params {
     uint32_t abi_version;  /* must be LBM_ABI_VERSION */
     uint32_t nx, ny;       /* lattice size, each >= 3; one time level of the
-                              populations (nx rounded up to 64, times ny, times 27
-                              values) must stay below 4 GiB */
+                              populations (nx, rounded up to 16 in FP32, times ny,
+                              rounded up to 64, times 27 values) must stay
+                              below 4 GiB */
     uint32_t precision;    /* LBM_FP64 or LBM_FP32_DEV */
     uint32_t bc[4];        /* boundary kind per side: x-lo, x-hi, y-lo, y-hi */
     uint32_t grad_mode;    /* 0: unit normal of the Allen-Cahn source and grad T of

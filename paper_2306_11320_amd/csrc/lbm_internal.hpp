@@ -9,10 +9,11 @@
 namespace lbm {
 
 // Population storage of one lattice, per time level: nodes are numbered
-// idx = y * pitch + x (x fastest, rows `pitch` nodes apart, pitch a multiple of
-// kBlock) and grouped in blocks of kBlock consecutive nodes; a block holds the
-// 27 populations (f_0..8, g_0..8, h_0..8) as 27 runs of kBlock values.  A level is
-// 27 * `plane` elements.  Levels A/B alternate every step.  f and h are stored
+// idx = y * pitch + x (x fastest; pitch = nx in FP64, nx rounded up to 16 in
+// FP32) and grouped in blocks of kBlock consecutive indices, so a block may
+// hold the end of one row and the start of the next; a block holds the 27
+// populations (f_0..8, g_0..8, h_0..8) as 27 runs of kBlock values.  A level
+// is 27 * `plane` elements, plane = pitch * ny rounded up to whole blocks.  Levels A/B alternate every step.  f and h are stored
 // as deviations from the rest equilibrium w_i phi0 and w_i T0; g as is.
 constexpr int kPlanes = 27;
 constexpr int kBlock = 64;

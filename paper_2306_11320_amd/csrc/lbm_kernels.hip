@@ -689,21 +689,23 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
     }
 }
 
-// Rows are padded to whole 64-node blocks, so the last block of a row whose
-// width is not a multiple of 64 holds padding slots that no node owns.  Left
-// unwritten, they leave the cache lines of every population run of that block
-// partly written each step, and the memory side has to merge the partial lines
-// (measured on the batched sweep: 0.61 ms per step, against 0.54 ms for the
-// same lattices widened to a multiple of 32 nodes).  A work-item whose node is
-// padding inside a line that real nodes also write stores zeros into its slots
-// of the next level, so every line is written whole.  Nothing reads padding.
+// Slots that no node owns: the few between a row's last node and the next
+// row's first (rows start on aligned boundaries) and the lattice's tail up to
+// the end of its last cache line.  Left unwritten, they would leave those
+// lines of every population run partly written each step, and the memory side
+// would have to merge them with their old contents.  A work-item whose node
+// lies beyond its row stores zeros into such slots of the next level.  Nothing
+// reads them.
 template <typename real>
 __device__ inline void pad_line(const Inst<real>& I, int dst, int gi, int gj)
 {
-    constexpr int line_nodes = 128 / (int)sizeof(real);
-    const int end = (I.nx + line_nodes - 1) / line_nodes * line_nodes;
-    if (gj >= I.ny || gi < I.nx || gi >= end) return;
-    const unsigned own = (unsigned)(gj * I.pitch + gi);
+    constexpr unsigned line_nodes = 128 / (unsigned)sizeof(real);
+    if (gj >= I.ny || gi < I.nx) return;
+    const unsigned nn = (unsigned)I.pitch * (unsigned)I.ny;
+    const unsigned own = (unsigned)gj * (unsigned)I.pitch + (unsigned)gi;
+    const bool gap = gi < I.pitch;
+    const bool tail = gj == I.ny - 1 && own < (nn + line_nodes - 1) / line_nodes * line_nodes;
+    if (!gap && !tail) return;
 #pragma unroll
     for (int q = 0; q < kPlanes; ++q) st(dst_plane(I, dst, q), noff<real>(own), real(0));
     st(to_global(I.jbase[0]), own * (unsigned)sizeof(real), real(0));

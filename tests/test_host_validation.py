@@ -34,11 +34,14 @@ def test_valid_lattice_workspace():
     L = _lib()
     p = _params()
     n = L.lbm_workspace_bytes(C.byref(p))
-    pitch = 64  # 40 rounded up to 32
-    plane = pitch * 24
+    plane = 48 * 24  # FP32 rows start every 16 nodes: 40 -> 48, 18 whole 64-node blocks
     assert n >= 2 * 27 * plane * 4 + 2 * plane * 4
     p64 = _params(precision=lbm.FP64)
-    assert L.lbm_workspace_bytes(C.byref(p64)) >= 2 * 27 * plane * 8
+    plane64 = 40 * 24  # FP64 rows packed with no gap: 960 nodes, 15 blocks
+    assert L.lbm_workspace_bytes(C.byref(p64)) >= 2 * 27 * plane64 * 8 + 2 * plane64 * 8
+    # a node count that is not a multiple of the block is rounded up to one
+    odd = _params(nx=41, ny=23, precision=lbm.FP64)
+    assert L.lbm_workspace_bytes(C.byref(odd)) >= 2 * 27 * 960 * 8 + 2 * 960 * 8
 
 
 @pytest.mark.parametrize("over,why", [
@@ -68,8 +71,9 @@ def test_rejected_parameters(over, why):
 
 @pytest.mark.parametrize("prec,word", [(lbm.FP32_DEV, 4), (lbm.FP64, 8)])
 def test_lattice_size_limit(prec, word):
-    """One time level (nx rounded up to 64, times ny, times 27 values) must stay
-    below 4 GiB: the kernels address a level with 32-bit byte offsets."""
+    """One time level (nx, rounded up to 16 in FP32, times ny, rounded up to
+    64, times 27 values) must stay below 4 GiB: the kernels address a level
+    with 32-bit byte offsets."""
     L = _lib()
     nx = 4096
     ny_max = (2 ** 32 - 1) // (nx * 27 * word)
