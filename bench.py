@@ -122,7 +122,7 @@ def time_gpu(items, prec, steps, warmup, tile=None, autotune=False, tune_cache=N
     ms = ev0.elapsed_time(ev1)
     d = lat.diagnostics()
     nodes = sum(c["nx"] * c["ny"] for c, _ in items)
-    tile_used = "x".join(str(v) for v in lbm.tile_shapes()[lat.tile()])
+    tile_used = lbm.tile_name(lat.tile())
     lat.close()
     return dict(ms_total=ms, wall_s=wall, ms_per_step=ms / steps, nodes=nodes, tuned=tuned, tile=tile_used,
                 mlups=nodes * steps / (ms * 1e-3) / 1e6, finite=d["n_nonfinite"] == 0, max_u=d["max_u"])

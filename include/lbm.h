@@ -277,7 +277,12 @@ int lbm_diagnostics_instance(lbm_ctx* c, int instance, lbm_diag* out);
 
 /* ---- launch configuration (autotuning) ---- */
 
-/* Number of compiled tile shapes and the shape of tile id (TX x TY nodes). */
+/* Number of compiled tile shapes and the shape of tile id (TX x TY nodes).
+ * The last id (tx = 512, ty = 0) steps every lattice that is periodic in x
+ * with 64 <= nx <= 256 in runs of 512 consecutive nodes in x-fastest order
+ * (one workgroup per run, so rows of any width leave no work-item idle) and
+ * the other lattices in 128 x 4 tiles; contexts holding a lattice with the
+ * potential form of the capillary force take 128 x 4 tiles throughout. */
 int lbm_tile_count(void);
 int lbm_tile_shape(int id, int* tx, int* ty);
 /* Selects the tile shape used by subsequent steps; invalidates captured graphs.

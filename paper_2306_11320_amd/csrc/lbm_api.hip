@@ -117,8 +117,30 @@ Layout make_layout(const lbm_params& p, size_t rsz, size_t& cursor)
     return L;
 }
 
-int tiles_of(const Layout& L, int t)
+// Step kernel of a set of lattices: 0 BGK only; 1 some lattice relaxes with
+// two relaxation times; 2 some lattice uses the potential form of the
+// capillary force.
+int step_variant(const lbm_params* ps, int n)
 {
+    int v = 0;
+    for (int k = 0; k < n; ++k) {
+        if (ps[k].collision == LBM_TRT && v < 1) v = 1;
+        if (ps[k].force_form == LBM_FORCE_POTENTIAL) v = 2;
+    }
+    return v;
+}
+
+// Whether tile id kTileRuns steps the lattice in runs (else in its tiles).
+bool runs_for(const lbm_params& p, int variant)
+{
+    return variant < 2 && p.bc[0] == LBM_BC_PERIODIC && p.nx >= (uint32_t)lbm::kRunMinNx &&
+           p.nx <= (uint32_t)lbm::kRunMaxNx;
+}
+
+int tiles_of(const Layout& L, const lbm_params& p, int variant, int t)
+{
+    if (t == lbm::kTileRuns && runs_for(p, variant))
+        return (int)(((long long)L.nx * L.ny + lbm::kRunNodes - 1) / lbm::kRunNodes);
     const int tx = lbm::kTileTX[t], ty = lbm::kTileTY[t];
     return ((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
 }
@@ -234,11 +256,12 @@ size_t plan(const lbm_params* ps, int n, std::vector<Layout>* lay, size_t* off_i
     size_t cursor = 0;
     std::vector<Layout> L;
     int tot[lbm::kTileCount] = {};
+    const int variant = step_variant(ps, n);
     for (int k = 0; k < n; ++k) {
         Layout l = make_layout(ps[k], rsz, cursor);
         for (int t = 0; t < lbm::kTileCount; ++t) {
             l.tile_off[t] = tot[t];
-            l.tile_cnt[t] = tiles_of(l, t);
+            l.tile_cnt[t] = tiles_of(l, ps[k], variant, t);
             tot[t] += l.tile_cnt[t];
         }
         L.push_back(l);
@@ -325,10 +348,7 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     c->ws = static_cast<char*>(d_ws);
     c->ws_bytes = ws_bytes;
     c->params.assign(ps, ps + n);
-    for (int k = 0; k < n; ++k) {
-        if (ps[k].collision == LBM_TRT && c->variant < 1) c->variant = 1;
-        if (ps[k].force_form == LBM_FORCE_POTENTIAL) c->variant = 2;
-    }
+    c->variant = step_variant(ps, n);
     c->lay = lay;
     c->grid = n > 1 ? -1 : 0;  // batched: persistent grid sized at the first step
     c->d_insts = c->ws + off_insts;
@@ -357,12 +377,23 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     };
     hipError_t e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), c->h_insts.size(), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return bail(fail(LBM_EHIP, "copy of lattice constants: %s", hipGetErrorString(e)));
-    // tile tables for every compiled shape, ordered by lattice then row-major tiles
+    // tile tables for every compiled shape, ordered by lattice then row-major
+    // tiles (or runs in node order)
     for (int t = 0; t < lbm::kTileCount; ++t) {
         std::vector<lbm::Tile> tl;
         for (int k = 0; k < n; ++k) {
             const int tx = lbm::kTileTX[t], ty = lbm::kTileTY[t];
             const int nx = lay[k].nx, ny = lay[k].ny;
+            if (t == lbm::kTileRuns && runs_for(ps[k], c->variant)) {
+                const long long nn = (long long)nx * ny;
+                for (long long n0 = 0; n0 < nn; n0 += lbm::kRunNodes) {
+                    const long long last = (n0 + lbm::kRunNodes < nn ? n0 + lbm::kRunNodes : nn) - 1;
+                    // interior: no node of the first or last row
+                    const bool inner = n0 / nx >= 1 && last / nx <= ny - 2;
+                    tl.push_back(lbm::Tile{k, (int)n0, 0, lbm::kTileRun | (inner ? lbm::kTileInterior : 0)});
+                }
+                continue;
+            }
             const bool px = ps[k].bc[0] == LBM_BC_PERIODIC, py = ps[k].bc[2] == LBM_BC_PERIODIC;
             for (int y = 0; y < ny; y += ty)
                 for (int x = 0; x < nx; x += tx) {
@@ -412,7 +443,8 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
         if (e != hipSuccess) return bail(fail(LBM_EHIP, "init: %s", hipGetErrorString(e)));
     }
     // (phi u) of the previous level := (phi u) now, so the first time derivative is zero
-    e = lbm::launch_fields((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile], c->ntiles[c->tile], 0, nullptr,
+    const int ft = lbm::grid_tile(c->tile);
+    e = lbm::launch_fields((int)c->prec, ft, c->d_insts, c->d_tiles[ft], c->ntiles[ft], 0, nullptr,
                            nullptr, nullptr, nullptr, nullptr, 0, 1, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return bail(fail(LBM_EHIP, "initial (phi u): %s", hipGetErrorString(e)));
@@ -494,8 +526,9 @@ int lbm_fields_instance(lbm_ctx* c, int instance, void* d_phi, void* d_ux, void*
     if (rc) return rc;
     if (out_dtype != LBM_OUT_F64 && out_dtype != LBM_OUT_F32) return fail(LBM_EINVAL, "unknown output dtype");
     const Layout& L = c->lay[instance];
-    HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile] + L.tile_off[c->tile],
-                               L.tile_cnt[c->tile], (int)(c->step & 1), d_phi, d_ux, d_uy, d_T, d_p,
+    const int ft = lbm::grid_tile(c->tile);
+    HIP_TRY(lbm::launch_fields((int)c->prec, ft, c->d_insts, c->d_tiles[ft] + L.tile_off[ft],
+                               L.tile_cnt[ft], (int)(c->step & 1), d_phi, d_ux, d_uy, d_T, d_p,
                                out_dtype == LBM_OUT_F32, 0, c->stream));
     return LBM_OK;
 }
@@ -514,18 +547,19 @@ int lbm_reinit_fields(lbm_ctx* c, int instance, const void* d_phi, const void* d
     const int lvl = (int)(c->step & 1);
     const size_t isz = inst_size(c->prec);
     const void* inst = static_cast<char*>(c->d_insts) + instance * isz;
-    const lbm::Tile* tiles = c->d_tiles[c->tile] + L.tile_off[c->tile];
+    const int ft = lbm::grid_tile(c->tile);
+    const lbm::Tile* tiles = c->d_tiles[ft] + L.tile_off[ft];
     // the other time level is free until the next step: it holds the staged
     // new fields (planes 0..4) and, when shifting, the current ones (5..9)
     double* staged = reinterpret_cast<double*>(c->ws + L.pop_off[lvl ^ 1]);
     HIP_TRY(lbm::launch_stage(d_phi, d_ux, d_uy, d_T, d_p, in_dtype == LBM_OUT_F32, n, staged, c->stream));
     if (mode == LBM_REINIT_SHIFT)
-        HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, tiles, L.tile_cnt[c->tile], lvl, staged + 5 * n,
+        HIP_TRY(lbm::launch_fields((int)c->prec, ft, c->d_insts, tiles, L.tile_cnt[ft], lvl, staged + 5 * n,
                                    staged + 6 * n, staged + 7 * n, staged + 8 * n, staged + 9 * n, 0, 0, c->stream));
     lbm::InitArgs ia{p.phi0_dev, p.T0_dev, 0.5 * (p.rho_l + p.rho_h), 0.5 * (p.rho_h - p.rho_l), d_p != nullptr,
                      mode == LBM_REINIT_SHIFT};
     HIP_TRY(lbm::launch_init((int)c->prec, inst, n, staged, ia, lvl, c->stream));
-    HIP_TRY(lbm::launch_fields((int)c->prec, c->tile, c->d_insts, tiles, L.tile_cnt[c->tile], lvl, nullptr, nullptr,
+    HIP_TRY(lbm::launch_fields((int)c->prec, ft, c->d_insts, tiles, L.tile_cnt[ft], lvl, nullptr, nullptr,
                                nullptr, nullptr, nullptr, 0, 1, c->stream));
     return LBM_OK;
 }
@@ -550,8 +584,9 @@ int lbm_diagnostics_instance(lbm_ctx* c, int instance, lbm_diag* out)
     }
     a.rcp_a = 0.5 * (p.rhocp_l + p.rhocp_h);
     a.rcp_b = 0.5 * (p.rhocp_h - p.rhocp_l);
-    HIP_TRY(lbm::launch_diag((int)c->prec, c->tile, c->d_insts, c->d_tiles[c->tile] + L.tile_off[c->tile],
-                             L.tile_cnt[c->tile], (int)(c->step & 1), a, c->d_partials, c->d_result, c->stream));
+    const int ft = lbm::grid_tile(c->tile);
+    HIP_TRY(lbm::launch_diag((int)c->prec, ft, c->d_insts, c->d_tiles[ft] + L.tile_off[ft],
+                             L.tile_cnt[ft], (int)(c->step & 1), a, c->d_partials, c->d_result, c->stream));
     double r[lbm::D_COUNT];
     HIP_TRY(hipMemcpyAsync(r, c->d_result, sizeof(r), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -809,8 +844,9 @@ int lbm_tile_count(void) { return lbm::kTileCount; }
 int lbm_tile_shape(int id, int* tx, int* ty)
 {
     if (id < 0 || id >= lbm::kTileCount) return fail(LBM_EINVAL, "tile id %d out of range", id);
-    if (tx) *tx = lbm::kTileTX[id];
-    if (ty) *ty = lbm::kTileTY[id];
+    // runs: tx = nodes per run, ty = 0
+    if (tx) *tx = id == lbm::kTileRuns ? lbm::kRunNodes : lbm::kTileTX[id];
+    if (ty) *ty = id == lbm::kTileRuns ? 0 : lbm::kTileTY[id];
     return LBM_OK;
 }
 

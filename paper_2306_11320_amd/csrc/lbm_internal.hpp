@@ -59,6 +59,9 @@ struct Tile {
 constexpr int kTileInterior = 1;
 // The tile lies inside the lattice (else its last columns or rows do not).
 constexpr int kTileWhole = 2;
+// The entry is a run: kRunNodes consecutive nodes in x-fastest order from node
+// number x0 (y0 unused).  Interior runs hold no node of the first or last row.
+constexpr int kTileRun = 4;
 
 // Sums accumulated by the FP64 diagnostics reduction, per lattice.
 enum DiagSlot {
@@ -79,10 +82,18 @@ struct InitArgs {
     int shift;  // add eq(new) - eq(current fields in staged planes 5..9) instead of replacing
 };
 
-// Compiled tile shapes (TX x TY nodes, one work-item per node).
-constexpr int kTileCount = 6;
-constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128};
-constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4};
+// Compiled tile shapes (TX x TY nodes, one work-item per node).  Id kTileRuns
+// steps lattices periodic in x with kRunMinNx <= nx <= kRunMaxNx in runs of
+// kRunNodes consecutive nodes (rows of any width then leave no work-item
+// idle) and the other lattices in its TX x TY tiles; it is not used with the
+// potential form of the capillary force (those lattices take tiles).
+constexpr int kTileCount = 7;
+constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128, 128};
+constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4, 4};
+constexpr int kTileRuns = 6;
+constexpr int kRunNodes = 512, kRunMinNx = 64, kRunMaxNx = 256;
+// Tile id whose TX x TY table serves the field and diagnostics kernels.
+constexpr int grid_tile(int id) { return id == kTileRuns ? 5 : id; }
 
 // Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
 // `variant` selects the step kernel: 0 BGK only; 1 BGK or two relaxation

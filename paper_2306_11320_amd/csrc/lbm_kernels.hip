@@ -26,6 +26,8 @@
 // block.
 #include "lbm_internal.hpp"
 
+#include <type_traits>
+
 namespace lbm {
 
 // Global-memory views of the lattice pointers: accesses through them compile
@@ -182,9 +184,8 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
 // Periodic image of a coordinate at most one period outside [0, n).
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <typename real, int TX, int TY, bool EDGE>
-__device__ inline void fill_entry(const Inst<real>& I, int src, Patch<real, TX, TY>& S, int q,
-                                  int gx, int gy)
+template <typename real, bool EDGE, typename P>
+__device__ inline void fill_entry(const Inst<real>& I, int src, P& S, int q, int gx, int gy)
 {
     int sx, sy;
     real aphi = 0, sphi = 1, aT = 0, sT = 1;
@@ -293,7 +294,7 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
 #pragma unroll
         for (int k = 0; k < 9; ++k) S.h[k][c] = h[k];
     } else if (used(lx, ly)) {
-        fill_entry<real, TX, TY, EDGE>(I, src, S, c, gi, gj);
+        fill_entry<real, EDGE>(I, src, S, c, gi, gj);
     }
     if (ring) {
         real sf = 0, sh = 0;
@@ -313,7 +314,7 @@ __device__ inline bool load_patch(const Inst<real>& I, int src, Patch<real, TX, 
     for (int q = EDGE ? tid : tid + TX * TY; q < PT::NRING; q += TX * TY) {
         int hx, hy;
         ring_coords<TX, TY>(q, hx, hy);
-        if (used(hx, hy)) fill_entry<real, TX, TY, EDGE>(I, src, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
+        if (used(hx, hy)) fill_entry<real, EDGE>(I, src, S, (hy + 1) * PT::PX + (hx + 1), x0 + hx, y0 + hy);
     }
     __syncthreads();
     return inside;
@@ -363,6 +364,17 @@ __device__ inline void fill_mu(const Inst<real>& I, int src, const Patch<real, T
     __syncthreads();
 }
 
+// Patch offsets of the eight neighbours of an entry, by direction k = 1..8:
+// fixed for a TX x TY tile patch of row length PX, per node for a run.
+template <int PX>
+struct GridNb {
+    __device__ static constexpr int at(int k) { return cy(k) * PX + cx(k); }
+};
+struct RunNb {
+    int o[9];
+    __device__ int at(int k) const { return o[k]; }
+};
+
 template <typename real>
 struct Macro {
     real dphi, phi, theta;
@@ -373,17 +385,17 @@ struct Macro {
 // Pass-1 quantities of one node from the patch and its own g_i.  POT: the
 // lattice may use the potential form of the capillary force, with mu_phi of the
 // patch in smu.
-template <typename real, int PX, bool POT = false>
+template <typename real, typename NB, bool POT = false>
 __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __restrict__ sphi,
-                                          const real* __restrict__ sT, int c, const real (&g)[9],
+                                          const real* __restrict__ sT, int c, const NB& nb, const real (&g)[9],
                                           const real* __restrict__ smu = nullptr)
 {
     Macro<real> m;
     const real pc = sphi[c];
-    const real pE = sphi[c + 1], pW = sphi[c - 1], pN = sphi[c + PX], pS = sphi[c - PX];
-    const real pNE = sphi[c + PX + 1], pNW = sphi[c + PX - 1], pSW = sphi[c - PX - 1], pSE = sphi[c - PX + 1];
-    const real tE = sT[c + 1], tW = sT[c - 1], tN = sT[c + PX], tS = sT[c - PX];
-    const real tNE = sT[c + PX + 1], tNW = sT[c + PX - 1], tSW = sT[c - PX - 1], tSE = sT[c - PX + 1];
+    const real pE = sphi[c + nb.at(1)], pW = sphi[c + nb.at(3)], pN = sphi[c + nb.at(2)], pS = sphi[c + nb.at(4)];
+    const real pNE = sphi[c + nb.at(5)], pNW = sphi[c + nb.at(6)], pSW = sphi[c + nb.at(7)], pSE = sphi[c + nb.at(8)];
+    const real tE = sT[c + nb.at(1)], tW = sT[c + nb.at(3)], tN = sT[c + nb.at(2)], tS = sT[c + nb.at(4)];
+    const real tNE = sT[c + nb.at(5)], tNW = sT[c + nb.at(6)], tSW = sT[c + nb.at(7)], tSE = sT[c + nb.at(8)];
     const real third = real(1.0 / 3.0), twelfth = real(1.0 / 12.0);
     // grad psi = 3 sum w_i c_i psi(x + c_i); lap psi = 6 sum_{i>0} w_i (psi(x + c_i) - psi(x))
     m.gpx = third * (pE - pW) + twelfth * ((pNE - pNW) + (pSE - pSW));
@@ -414,8 +426,8 @@ __device__ inline Macro<real> node_macros(const Inst<real>& I, const real* __res
     const real sdp = gsx * m.gpx + gsy * m.gpy;
     if (POT && I.force_form == 1) {
         // potential form: -phi grad mu_phi in place of mu_phi grad phi
-        const real mE = smu[c + 1], mW = smu[c - 1], mN = smu[c + PX], mS = smu[c - PX];
-        const real mNE = smu[c + PX + 1], mNW = smu[c + PX - 1], mSW = smu[c - PX - 1], mSE = smu[c - PX + 1];
+        const real mE = smu[c + nb.at(1)], mW = smu[c + nb.at(3)], mN = smu[c + nb.at(2)], mS = smu[c + nb.at(4)];
+        const real mNE = smu[c + nb.at(5)], mNW = smu[c + nb.at(6)], mSW = smu[c + nb.at(7)], mSE = smu[c + nb.at(8)];
         const real gmx = third * (mE - mW) + twelfth * ((mNE - mNW) + (mSE - mSW));
         const real gmy = third * (mN - mS) + twelfth * ((mNE + mNW) - (mSW + mSE));
         const real sp = sig * I.inv_W2 * phi;
@@ -612,12 +624,11 @@ __device__ __forceinline__ void collide_dir(const Inst<real>& I, const Macro<rea
 // populations are f, g, h.  The thermal update at the destination y = x + c_i
 // is h_i(y, t+1) = [h*_i(x) + (rho c_p(y) - 1) h_i(y, t)] / rho c_p(y).
 // Each direction is stored as soon as it is collided.
-template <typename real, int TX, int TY, bool EDGE, bool TRT, bool POT>
-__device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<real, TX, TY>& S, const real* smu, int gi,
+template <typename real, bool EDGE, bool TRT, bool POT, typename P, typename NB>
+__device__ __forceinline__ void node_update(const Inst<real>& I, const P& S, const NB& nb, const real* smu, int gi,
                                             int gj, int c, int dst, const real (&f)[9], const real (&g)[9],
                                             const real (&h)[9], real jpx, real jpy)
 {
-    constexpr int PX = Patch<real, TX, TY>::PX;
     const unsigned own = (unsigned)(gj * I.pitch + gi);
     const gptr<real> Jx = to_global(I.jbase[0]), Jy = to_global(I.jbase[1]);
     // destination rows and columns of the interior path (periodic wrap only)
@@ -631,7 +642,7 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
         dcol[2] = (unsigned)wrap1(gi + 1, I.nx);
     }
 
-    const Macro<real> m = node_macros<real, PX, POT>(I, S.phi, S.T, c, g, smu);
+    const Macro<real> m = node_macros<real, NB, POT>(I, S.phi, S.T, c, nb, g, smu);
     real jx, jy;
     const Pre<real> q = pre_collide<real, TRT>(I, m, f, h, jpx, jpy, jx, jy);
     st(Jx, own * (unsigned)sizeof(real), jx);
@@ -649,7 +660,7 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const Patch<rea
         if (EDGE) in_lattice = dest<real, EDGE>(I, gi, gj, k, di, side);
         else di = drow[cy(k) + 1] + dcol[cx(k) + 1];
         if (in_lattice) {
-            const int cd = c + cy(k) * PX + cx(k);
+            const int cd = c + nb.at(k);
             st(dst_plane(I, dst, kF + k), noff<real>(di), (real)(fsk));
             st(dst_plane(I, dst, kG + k), noff<real>(di), (real)(gsk));
             const real hold = S.h[k][cd];
@@ -731,8 +742,10 @@ __device__ __forceinline__ void tile_step(const Inst<real>& I, int x0, int y0, i
         if (!WHOLE) pad_line(I, src ^ 1, x0 + tid % TX, y0 + tid / TX);
         return;
     }
-    const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-    node_update<real, TX, TY, EDGE, TRT, POT>(I, S, smu, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h, jpx, jpy);
+    constexpr int PX = Patch<real, TX, TY>::PX;
+    const int c = (tid / TX + 1) * PX + (tid % TX + 1);
+    node_update<real, EDGE, TRT, POT>(I, S, GridNb<PX>{}, smu, x0 + tid % TX, y0 + tid / TX, c, src ^ 1, f, g, h, jpx,
+                                      jpy);
 }
 
 // Interior tiles take the wrap-only path; a whole one needs no per-node
@@ -782,6 +795,232 @@ __device__ __forceinline__ bool load_any(const Inst<real>& I, const Tile& tl, in
     return load_patch<real, TX, TY, true, false>(I, src, S, tl.x0, tl.y0, f, g, h, jpx, jpy);
 }
 
+// ---- runs ----
+// A run is kRunNodes consecutive nodes of a lattice in x-fastest order (node
+// number n = y nx + x), one per work-item, so rows of any width leave no
+// work-item idle.  Used for lattices periodic in x with
+// kRunMinNx <= nx <= kRunMaxNx.  The patch of a run starting at n0 is the
+// window of node numbers n0 - nx - 1 ... n0 + kRunNodes + nx (window slot
+// w = m - n0 + nx + 1 for node number m), which holds every neighbour of the
+// run's nodes in the rows below and above.  A neighbour across the periodic x
+// boundary sits nx - 1 or nx + 1 slots away from where it would be without the
+// wrap; the two that can fall outside the window, (0, y - 1) of the first
+// node with x = nx - 1 and (nx - 1, y + 1) of the last node with x = 0, get
+// slots of their own at the end.  Slots of rows -1 and ny are the ghosts of
+// the boundary rules (runs holding no node of the first or last row never
+// read them).  The four corner ghosts (-1, -1), (nx, -1), (-1, ny), (nx, ny)
+// also get slots of their own: a wall's rule is evaluated at the unwrapped
+// coordinate along the wall (a Dirichlet temperature at -1 or nx), as for
+// every other ghost of a tile's ring.
+template <typename real>
+struct RunPatch {
+    static constexpr int NW = kRunNodes + 2 * kRunMaxNx + 8;
+    static constexpr int GLO = NW - 6, GHI = NW - 5;
+    static constexpr int CSW = NW - 4, CSE = NW - 3, CNW = NW - 2, CNE = NW - 1;
+    real phi[NW];
+    real T[NW];
+    real irc[NW];
+    real h[9][NW];
+};
+
+template <typename real, int TX, int TY>
+union StepLDS {
+    Patch<real, TX, TY> tile;
+    RunPatch<real> run;
+};
+
+// Window slot and lattice point of ring entry q of the run from n0 (q in
+// [0, 2 nx + 4), and in EDGE runs also [2 nx + 4, 2 nx + 8): the slots below
+// the run, those above it, the two wrap slots, then the four corner ghosts).
+// Returns whether a node of the run may read the entry: EDGE runs read rows
+// -1 .. ny, interior runs rows 0 .. ny - 1 only.
+template <bool EDGE>
+__device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, int& w, int& gx, int& gy)
+{
+    using RP = RunPatch<float>;
+    if (EDGE && q >= 2 * nx + 4) {
+        const int k = q - (2 * nx + 4);
+        w = RP::CSW + k;
+        gx = (k & 1) ? nx : -1;
+        gy = (k & 2) ? ny : -1;
+        return true;
+    }
+    if (q < 2 * nx + 2) {
+        w = q < nx + 1 ? q : q + kRunNodes;
+        const int m = n0 - nx - 1 + w;
+        if (m < -nx) return false;
+        gy = (m + nx) / nx - 1;
+        gx = m - gy * nx;
+        return EDGE ? gy <= ny : (gy >= 0 && gy < ny);
+    }
+    const int y0 = n0 / nx, x0 = n0 - y0 * nx;
+    if (q == 2 * nx + 2) {
+        // (0, y0 - 1): south-east neighbour of the first node with x = nx - 1,
+        // outside the window when that node is among the first nx - 2
+        w = RP::GLO;
+        gx = 0;
+        gy = y0 - 1;
+        return x0 >= 2;
+    }
+    // (nx - 1, yl + 1): north-west neighbour of the last node with x = 0 (row
+    // yl of the run's last node), outside the window when that node is among
+    // the last nx - 2 slots of the run
+    const int yl = w_hi_first;
+    w = RP::GHI;
+    gx = nx - 1;
+    gy = yl + 1;
+    return yl * nx - n0 >= kRunNodes - nx + 2;
+}
+
+// Plain fill of a run window slot from lattice point (gx, gy) inside the lattice.
+template <typename real>
+__device__ inline void run_load_entry(const Inst<real>& I, int src, RunPatch<real>& R, int w, int gx, int gy,
+                                      real (&rf)[9], real (&rh)[9])
+{
+    const unsigned idx = (unsigned)(gy * I.pitch + gx);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        rf[k] = ld(src_plane(I, src, kF + k), noff<real>(idx));
+        rh[k] = ld(src_plane(I, src, kH + k), noff<real>(idx));
+    }
+    (void)R; (void)w;
+}
+
+template <typename real>
+__device__ inline void run_store_entry(RunPatch<real>& R, const Inst<real>& I, int w, const real (&rf)[9],
+                                       const real (&rh)[9])
+{
+    real sf = 0, sh = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        sf += rf[k];
+        sh += rh[k];
+    }
+    R.phi[w] = sf;
+    R.T[w] = sh;
+    R.irc[w] = recip(I.rcp_a + I.rcp_b * (I.phi0 + sf));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R.h[k][w] = rh[k];
+}
+
+// Loads the work-item's own node of the run from n0 and fills the window.
+// Returns whether the node lies in the lattice; (x, y) its coordinates.  In
+// interior runs the first kRunNodes ring entries go one per work-item and
+// their loads are issued together with the node's own.
+template <typename real, bool EDGE>
+__device__ inline bool load_run(const Inst<real>& I, int src, RunPatch<real>& R, int n0, int& x, int& y,
+                                real (&f)[9], real (&g)[9], real (&h)[9], real& jpx, real& jpy)
+{
+    const int nx = I.nx, ny = I.ny, nn = nx * ny;
+    const int t = threadIdx.x;
+    const int n = n0 + t;
+    const bool inside = n < nn;
+    y = n / nx;
+    x = n - y * nx;
+    const int c = t + nx + 1;
+    const int nring = 2 * nx + (EDGE ? 8 : 4);
+    const int last = (n0 + kRunNodes < nn ? n0 + kRunNodes : nn) - 1;
+    const int yl = last / nx;
+
+    int rw = 0, rgx = 0, rgy = 0;
+    const bool ring = !EDGE && t < nring && run_ring<false>(t, n0, nx, ny, yl, rw, rgx, rgy);
+    real rf[9], rh[9];
+    if (ring) run_load_entry(I, src, R, rw, rgx, rgy, rf, rh);
+    if (inside) {
+        const unsigned idx = (unsigned)(y * I.pitch + x);
+        real sf = 0, sh = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f[k] = ld(src_plane(I, src, kF + k), noff<real>(idx));
+            h[k] = ld(src_plane(I, src, kH + k), noff<real>(idx));
+            g[k] = ld(src_plane(I, src, kG + k), noff<real>(idx));
+        }
+        jpx = ld(to_global<const real>(I.jbase[0]), idx * (unsigned)sizeof(real));
+        jpy = ld(to_global<const real>(I.jbase[1]), idx * (unsigned)sizeof(real));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sf += f[k];
+            sh += h[k];
+        }
+        R.phi[c] = sf;
+        R.T[c] = sh;
+        R.irc[c] = recip(I.rcp_a + I.rcp_b * (I.phi0 + sf));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R.h[k][c] = h[k];
+    } else if (EDGE && y == ny) {
+        // beyond the lattice's last node: the slot is a ghost of row ny
+        fill_entry<real, true>(I, src, R, c, x, y);
+    }
+    if (ring) run_store_entry(R, I, rw, rf, rh);
+    for (int q = EDGE ? t : t + kRunNodes; q < nring; q += kRunNodes) {
+        int w, gx, gy;
+        if (!run_ring<EDGE>(q, n0, nx, ny, yl, w, gx, gy)) continue;
+        if (EDGE) {
+            fill_entry<real, true>(I, src, R, w, gx, gy);
+        } else {
+            real qf[9], qh[9];
+            run_load_entry(I, src, R, w, gx, gy, qf, qh);
+            run_store_entry(R, I, w, qf, qh);
+        }
+    }
+    __syncthreads();
+    return inside;
+}
+
+// Slots between a row's last node and the next row's first (FP32 rows start
+// on 64-byte boundaries) and the lattice's tail up to the end of its last cache
+// line: the row's last nodes store zeros into them in the next level, so no
+// line is left partly written.
+template <typename real>
+__device__ inline void run_pad(const Inst<real>& I, int dst, int x, int y)
+{
+    constexpr unsigned line_nodes = 128 / (unsigned)sizeof(real);
+    int ext = I.pitch - I.nx;
+    if (y == I.ny - 1) {
+        const unsigned nn = (unsigned)I.pitch * (unsigned)I.ny;
+        ext += (int)((nn + line_nodes - 1) / line_nodes * line_nodes - nn);
+    }
+    if (ext == 0 || x < I.nx - ext) return;
+    const unsigned own = (unsigned)(y * I.pitch + I.nx + (x - (I.nx - ext)));
+#pragma unroll
+    for (int q = 0; q < kPlanes; ++q) st(dst_plane(I, dst, q), noff<real>(own), real(0));
+    st(to_global(I.jbase[0]), own * (unsigned)sizeof(real), real(0));
+    st(to_global(I.jbase[1]), own * (unsigned)sizeof(real), real(0));
+}
+
+template <typename real, bool EDGE, bool TRT>
+__device__ __forceinline__ void run_step(const Inst<real>& I, int n0, int src, RunPatch<real>& R)
+{
+    using RP = RunPatch<real>;
+    real f[9], g[9], h[9], jpx = 0, jpy = 0;
+    int x, y;
+    const bool inside = load_run<real, EDGE>(I, src, R, n0, x, y, f, g, h, jpx, jpy);
+    if (!inside) return;
+    const int nx = I.nx, t = threadIdx.x, c = t + nx + 1;
+    const bool xl = x == 0, xr = x == nx - 1;
+    // corner ghosts (EDGE runs only hold nodes of the first or last row)
+    const bool bot = EDGE && y == 0, top = EDGE && y == I.ny - 1;
+    RunNb nb;
+    nb.o[0] = 0;
+    nb.o[1] = xr ? 1 - nx : 1;
+    nb.o[2] = nx;
+    nb.o[3] = xl ? nx - 1 : -1;
+    nb.o[4] = -nx;
+    nb.o[5] = xr ? (top ? RP::CNE - c : 1) : nx + 1;
+    nb.o[6] = xl ? (top ? RP::CNW - c : (t < kRunNodes - nx + 2 ? 2 * nx - 1 : RP::GHI - c)) : nx - 1;
+    nb.o[7] = xl ? (bot ? RP::CSW - c : -1) : -nx - 1;
+    nb.o[8] = xr ? (bot ? RP::CSE - c : (t >= nx - 2 ? 1 - 2 * nx : RP::GLO - c)) : 1 - nx;
+    run_pad(I, src ^ 1, x, y);
+    node_update<real, EDGE, TRT, false>(I, R, nb, nullptr, x, y, c, src ^ 1, f, g, h, jpx, jpy);
+}
+
+template <typename real, bool TRT>
+__device__ __forceinline__ void run_any(const Inst<real>& I, const Tile& tl, int src, RunPatch<real>& R)
+{
+    if (tl.flags & kTileInterior) run_step<real, false, TRT>(I, tl.x0, src, R);
+    else run_step<real, true, TRT>(I, tl.x0, src, R);
+}
+
 // Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
 // the 8 XCDs; renumbering them so each XCD gets a contiguous block of logical
 // ids keeps vertically adjacent tiles (which share ring rows) in one L2.
@@ -799,12 +1038,16 @@ __device__ inline void my_tiles(int ntiles, int& t0, int& t1)
 // VAR 1: some lattice uses two relaxation times; VAR 2: some lattice uses the
 // potential form of the capillary force (extra LDS, a second ring of phi).
 // Separate kernels, so that the BGK-only kernel keeps its own register budget.
-template <typename real, int TX, int TY, int VAR>
+// RUNS: the table may also hold runs (kTileRun entries; TX * TY == kRunNodes,
+// BGK or two relaxation times only); tile and run patches share the LDS.
+template <typename real, int TX, int TY, int VAR, bool RUNS = false>
 __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
                                                   int ntiles, int src)
 {
     constexpr bool ANY_TRT = VAR >= 1;
-    __shared__ Patch<real, TX, TY> S;
+    static_assert(!RUNS || (TX * TY == kRunNodes && VAR < 2), "runs: one node per work-item, no potential form");
+    using LDS = typename std::conditional<RUNS, StepLDS<real, TX, TY>, Patch<real, TX, TY>>::type;
+    __shared__ LDS U;
     int t0, t1;
     my_tiles(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
@@ -815,10 +1058,19 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
         tl.y0 = __builtin_amdgcn_readfirstlane(tl.y0);
         tl.flags = __builtin_amdgcn_readfirstlane(tl.flags);
         const Inst<real>& I = insts[tl.inst];
+        Patch<real, TX, TY>* Sp;
+        if constexpr (RUNS) Sp = &U.tile;
+        else Sp = &U;
+        Patch<real, TX, TY>& S = *Sp;
         if constexpr (VAR == 2) {
             __shared__ PotLDS<real, TX, TY> Q;
             if (I.collision == 0) tile_pot<real, TX, TY, false>(I, tl, src, S, Q);
             else tile_pot<real, TX, TY, true>(I, tl, src, S, Q);
+        } else if (RUNS && (tl.flags & kTileRun)) {
+            if constexpr (RUNS) {
+                if (!ANY_TRT || I.collision == 0) run_any<real, false>(I, tl, src, U.run);
+                else run_any<real, true>(I, tl, src, U.run);
+            }
         } else {
             if (!ANY_TRT || I.collision == 0) tile_any<real, TX, TY, false>(I, tl, src, S);
             else tile_any<real, TX, TY, true>(I, tl, src, S);
@@ -851,8 +1103,9 @@ __global__ __launch_bounds__(TX* TY) void k_fields(const Inst<real>* __restrict_
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
-            const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX, true>(I, S.phi, S.T, c, g, Q.mu);
+            constexpr int PX = Patch<real, TX, TY>::PX;
+            const int c = (tid / TX + 1) * PX + (tid % TX + 1);
+            const Macro<real> m = node_macros<real, GridNb<PX>, true>(I, S.phi, S.T, c, GridNb<PX>{}, g, Q.mu);
             if (jprev_out) {
                 const long long own = (long long)gj * I.pitch + gi;
                 const gptr<real> J = to_global(I.jprev);
@@ -997,8 +1250,9 @@ __global__ __launch_bounds__(TX* TY) void k_diag(const Inst<real>* __restrict__ 
         if (inside) {
             const int tid = threadIdx.x;
             const int gi = tl.x0 + tid % TX, gj = tl.y0 + tid / TX;
-            const int c = (tid / TX + 1) * Patch<real, TX, TY>::PX + (tid % TX + 1);
-            const Macro<real> m = node_macros<real, Patch<real, TX, TY>::PX, true>(I, S.phi, S.T, c, g, Q.mu);
+            constexpr int PX = Patch<real, TX, TY>::PX;
+            const int c = (tid / TX + 1) * PX + (tid % TX + 1);
+            const Macro<real> m = node_macros<real, GridNb<PX>, true>(I, S.phi, S.T, c, GridNb<PX>{}, g, Q.mu);
             const double phi = (double)I.phi0 + (double)m.dphi;
             const double T = (double)I.T0 + (double)m.theta;
             const double ux = m.ux, uy = m.uy, p = m.p;
@@ -1099,18 +1353,19 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 
 // ---- launchers ----
 
-template <typename real, int TX, int TY>
+template <typename real, int TX, int TY, bool RUNS = false>
 static hipError_t step_t(const void* insts, const Tile* tiles, int ntiles, int grid, int src, int variant,
                          hipStream_t s)
 {
     const int G = grid > 0 ? grid : ntiles;
     const Inst<real>* ip = static_cast<const Inst<real>*>(insts);
+    // a table for lattices with the potential form holds no runs
     if (variant == 2)
         hipLaunchKernelGGL((k_step<real, TX, TY, 2>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
     else if (variant == 1)
-        hipLaunchKernelGGL((k_step<real, TX, TY, 1>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
+        hipLaunchKernelGGL((k_step<real, TX, TY, 1, RUNS>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
     else
-        hipLaunchKernelGGL((k_step<real, TX, TY, 0>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
+        hipLaunchKernelGGL((k_step<real, TX, TY, 0, RUNS>), dim3(G), dim3(TX * TY), 0, s, ip, tiles, ntiles, src);
     return hipGetLastError();
 }
 
@@ -1136,7 +1391,8 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     return hipGetLastError();
 }
 
-// Tile id -> (TX, TY), in the order of kTileTX and kTileTY.
+// Tile id -> (TX, TY), in the order of kTileTX and kTileTY (the field and
+// diagnostics kernels take grid_tile(id)).
 #define LBM_TILE_SWITCH(TILE, CALL)                  \
     switch (TILE) {                                  \
     case 0: return CALL(64, 4);                      \
@@ -1147,30 +1403,40 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     case 5: return CALL(128, 4);                     \
     default: return hipErrorInvalidValue;            \
     }
+static_assert(kTileTX[kTileRuns] * kTileTY[kTileRuns] == kRunNodes && kTileTX[kTileRuns] == 128 &&
+                  kTileTY[kTileRuns] == 4 && grid_tile(kTileRuns) == 5,
+              "the run kernel is the 128 x 4 kernel");
 
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
                        int variant, hipStream_t s)
 {
 #define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, variant, s)
 #define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, variant, s)
+    if (tile == kTileRuns)
+        return prec == 0 ? step_t<double, 128, 4, true>(insts, tiles, ntiles, grid, src, variant, s)
+                         : step_t<float, 128, 4, true>(insts, tiles, ntiles, grid, src, variant, s);
     if (prec == 0) { LBM_TILE_SWITCH(tile, STEP64) }
     LBM_TILE_SWITCH(tile, STEP32)
 #undef STEP64
 #undef STEP32
 }
 
-template <typename real, int TX, int TY>
+template <typename real, int TX, int TY, bool RUNS = false>
 static hipError_t occ_t(int* blocks, int variant)
 {
     if (variant == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 2>, TX * TY, 0);
-    if (variant == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 1>, TX * TY, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 0>, TX * TY, 0);
+    if (variant == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 1, RUNS>, TX * TY, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<real, TX, TY, 0, RUNS>, TX * TY, 0);
 }
 
 hipError_t step_occupancy(int prec, int tile, int variant, int* blocks_per_cu)
 {
 #define O64(a, b) occ_t<double, a, b>(blocks_per_cu, variant)
 #define O32(a, b) occ_t<float, a, b>(blocks_per_cu, variant)
+    if (tile == kTileRuns)
+        return prec == 0 ? occ_t<double, 128, 4, true>(blocks_per_cu, variant)
+                         : occ_t<float, 128, 4, true>(blocks_per_cu, variant);
     if (prec == 0) { LBM_TILE_SWITCH(tile, O64) }
     LBM_TILE_SWITCH(tile, O32)
 #undef O64

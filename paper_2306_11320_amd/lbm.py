@@ -397,6 +397,7 @@ class Lattice:
 
 
 def tile_shapes() -> list[tuple[int, int]]:
+    """(TX, TY) of every tile id; (512, 0) marks runs of 512 consecutive nodes."""
     L = lib()
     out = []
     for t in range(L.lbm_tile_count()):
@@ -404,6 +405,11 @@ def tile_shapes() -> list[tuple[int, int]]:
         _check(L.lbm_tile_shape(t, C.byref(tx), C.byref(ty)))
         out.append((tx.value, ty.value))
     return out
+
+
+def tile_name(t: int) -> str:
+    tx, ty = tile_shapes()[t]
+    return f"runs of {tx} nodes" if ty == 0 else f"{tx}x{ty}"
 
 
 def copy_probe(src, dst, stream) -> None:
