@@ -88,7 +88,8 @@ enum { LBM_OUT_F64 = 0, LBM_OUT_F32 = 1 };
 typedef struct lbm_params {
     uint32_t abi_version;  /* must be LBM_ABI_VERSION */
     uint32_t nx, ny;       /* lattice size, each >= 3; one time level of the
-                              populations (nx, rounded up to 16 in FP32, times ny,
+                              populations (nx, rounded up to 16 in FP32 unless x
+                              is periodic and 64 <= nx <= 256, times ny,
                               rounded up to 64, times 27 values) must stay
                               below 4 GiB */
     uint32_t precision;    /* LBM_FP64 or LBM_FP32_DEV */
@@ -278,11 +279,12 @@ int lbm_diagnostics_instance(lbm_ctx* c, int instance, lbm_diag* out);
 /* ---- launch configuration (autotuning) ---- */
 
 /* Number of compiled tile shapes and the shape of tile id (TX x TY nodes).
- * The last id (tx = 512, ty = 0) steps every lattice that is periodic in x
- * with 64 <= nx <= 256 in runs of 512 consecutive nodes in x-fastest order
- * (one workgroup per run, so rows of any width leave no work-item idle) and
- * the other lattices in 128 x 4 tiles; contexts holding a lattice with the
- * potential form of the capillary force take 128 x 4 tiles throughout. */
+ * The last two ids (tx = 512 or 256, ty = 0) step every lattice that is
+ * periodic in x with 64 <= nx <= 256 in runs of tx consecutive nodes in
+ * x-fastest order (one workgroup per run, so rows of any width leave no
+ * work-item idle) and the other lattices in 128 x 4 or 64 x 4 tiles; contexts
+ * holding a lattice with the potential form of the capillary force take those
+ * tiles throughout. */
 int lbm_tile_count(void);
 int lbm_tile_shape(int id, int* tx, int* ty);
 /* Selects the tile shape used by subsequent steps; invalidates captured graphs.

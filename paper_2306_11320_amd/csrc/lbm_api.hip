@@ -38,7 +38,8 @@ int fail(int code, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 // Nodes per row boundary: FP32 rows start on 64-byte boundaries of a
-// population run, FP64 rows are packed with no gap (see make_layout).
+// population run, FP64 rows are packed with no gap; rows of lattices that runs
+// can step are packed in both (see make_layout).
 int row_align(size_t rsz) { return rsz == 8 ? 1 : 16; }
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -94,29 +95,6 @@ int validate(const lbm_params& p)
     return LBM_OK;
 }
 
-Layout make_layout(const lbm_params& p, size_t rsz, size_t& cursor)
-{
-    Layout L{};
-    L.nx = (int)p.nx;
-    L.ny = (int)p.ny;
-    // Rows are not padded to whole blocks: a row whose width is not a multiple
-    // of the block shares its last block with the next row, so no slot that
-    // no node owns is moved (measured on the batched sweep, FP64: 1.15 ->
-    // 1.07 ms per step).  In FP32, rows whose starts are not 8-byte aligned
-    // were measured up to 10% slower; there rows start on 64-byte boundaries
-    // (at most 15 slots between rows, written as zeros by the step).
-    L.pitch = (int)align_up(p.nx, (size_t)row_align(rsz));
-    L.plane = (long long)align_up(align_up((size_t)L.pitch * p.ny, lbm::kBlock), kAlign / rsz);
-    const size_t level = (size_t)lbm::kPlanes * L.plane * rsz;
-    L.pop_off[0] = cursor;
-    cursor = align_up(cursor + level, kAlign);
-    L.pop_off[1] = cursor;
-    cursor = align_up(cursor + level, kAlign);
-    L.jprev_off = cursor;
-    cursor = align_up(cursor + 2 * (size_t)L.plane * rsz, kAlign);
-    return L;
-}
-
 // Step kernel of a set of lattices: 0 BGK only; 1 some lattice relaxes with
 // two relaxation times; 2 some lattice uses the potential form of the
 // capillary force.
@@ -130,17 +108,43 @@ int step_variant(const lbm_params* ps, int n)
     return v;
 }
 
-// Whether tile id kTileRuns steps the lattice in runs (else in its tiles).
+// Whether the run tile ids step the lattice in runs (else in its tiles).
 bool runs_for(const lbm_params& p, int variant)
 {
     return variant < 2 && p.bc[0] == LBM_BC_PERIODIC && p.nx >= (uint32_t)lbm::kRunMinNx &&
            p.nx <= (uint32_t)lbm::kRunMaxNx;
 }
 
+Layout make_layout(const lbm_params& p, size_t rsz, int variant, size_t& cursor)
+{
+    Layout L{};
+    L.nx = (int)p.nx;
+    L.ny = (int)p.ny;
+    // Rows are not padded to whole blocks: a row whose width is not a multiple
+    // of the block shares its last block with the next row, so no slot that
+    // no node owns is moved (measured on the batched sweep, FP64: 1.15 ->
+    // 1.07 ms per step).  In FP32, tiles on rows whose starts are not 8-byte
+    // aligned were measured up to 10% slower; there rows start on 64-byte
+    // boundaries (at most 15 slots between rows, written as zeros by the
+    // step), except in lattices that runs can step: packed rows keep a run's
+    // nodes contiguous in memory, so every wavefront of a run reads whole
+    // aligned runs of 64 values (width 221: 51.5 -> 45.5 ps per node).
+    L.pitch = runs_for(p, variant) ? (int)p.nx : (int)align_up(p.nx, (size_t)row_align(rsz));
+    L.plane = (long long)align_up(align_up((size_t)L.pitch * p.ny, lbm::kBlock), kAlign / rsz);
+    const size_t level = (size_t)lbm::kPlanes * L.plane * rsz;
+    L.pop_off[0] = cursor;
+    cursor = align_up(cursor + level, kAlign);
+    L.pop_off[1] = cursor;
+    cursor = align_up(cursor + level, kAlign);
+    L.jprev_off = cursor;
+    cursor = align_up(cursor + 2 * (size_t)L.plane * rsz, kAlign);
+    return L;
+}
+
 int tiles_of(const Layout& L, const lbm_params& p, int variant, int t)
 {
-    if (t == lbm::kTileRuns && runs_for(p, variant))
-        return (int)(((long long)L.nx * L.ny + lbm::kRunNodes - 1) / lbm::kRunNodes);
+    const int rn = lbm::run_nodes(t);
+    if (rn && runs_for(p, variant)) return (int)(((long long)L.nx * L.ny + rn - 1) / rn);
     const int tx = lbm::kTileTX[t], ty = lbm::kTileTY[t];
     return ((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
 }
@@ -258,7 +262,7 @@ size_t plan(const lbm_params* ps, int n, std::vector<Layout>* lay, size_t* off_i
     int tot[lbm::kTileCount] = {};
     const int variant = step_variant(ps, n);
     for (int k = 0; k < n; ++k) {
-        Layout l = make_layout(ps[k], rsz, cursor);
+        Layout l = make_layout(ps[k], rsz, variant, cursor);
         for (int t = 0; t < lbm::kTileCount; ++t) {
             l.tile_off[t] = tot[t];
             l.tile_cnt[t] = tiles_of(l, ps[k], variant, t);
@@ -384,10 +388,11 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
         for (int k = 0; k < n; ++k) {
             const int tx = lbm::kTileTX[t], ty = lbm::kTileTY[t];
             const int nx = lay[k].nx, ny = lay[k].ny;
-            if (t == lbm::kTileRuns && runs_for(ps[k], c->variant)) {
+            const int rn = lbm::run_nodes(t);
+            if (rn && runs_for(ps[k], c->variant)) {
                 const long long nn = (long long)nx * ny;
-                for (long long n0 = 0; n0 < nn; n0 += lbm::kRunNodes) {
-                    const long long last = (n0 + lbm::kRunNodes < nn ? n0 + lbm::kRunNodes : nn) - 1;
+                for (long long n0 = 0; n0 < nn; n0 += rn) {
+                    const long long last = (n0 + rn < nn ? n0 + rn : nn) - 1;
                     // interior: no node of the first or last row
                     const bool inner = n0 / nx >= 1 && last / nx <= ny - 2;
                     tl.push_back(lbm::Tile{k, (int)n0, 0, lbm::kTileRun | (inner ? lbm::kTileInterior : 0)});
@@ -845,8 +850,9 @@ int lbm_tile_shape(int id, int* tx, int* ty)
 {
     if (id < 0 || id >= lbm::kTileCount) return fail(LBM_EINVAL, "tile id %d out of range", id);
     // runs: tx = nodes per run, ty = 0
-    if (tx) *tx = id == lbm::kTileRuns ? lbm::kRunNodes : lbm::kTileTX[id];
-    if (ty) *ty = id == lbm::kTileRuns ? 0 : lbm::kTileTY[id];
+    const int rn = lbm::run_nodes(id);
+    if (tx) *tx = rn ? rn : lbm::kTileTX[id];
+    if (ty) *ty = rn ? 0 : lbm::kTileTY[id];
     return LBM_OK;
 }
 

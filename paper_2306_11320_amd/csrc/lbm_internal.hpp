@@ -9,8 +9,8 @@
 namespace lbm {
 
 // Population storage of one lattice, per time level: nodes are numbered
-// idx = y * pitch + x (x fastest; pitch = nx in FP64, nx rounded up to 16 in
-// FP32) and grouped in blocks of kBlock consecutive indices, so a block may
+// idx = y * pitch + x (x fastest; pitch = nx in FP64 and in lattices that runs
+// can step, else nx rounded up to 16 in FP32) and grouped in blocks of kBlock consecutive indices, so a block may
 // hold the end of one row and the start of the next; a block holds the 27
 // populations (f_0..8, g_0..8, h_0..8) as 27 runs of kBlock values.  A level
 // is 27 * `plane` elements, plane = pitch * ny rounded up to whole blocks.  Levels A/B alternate every step.  f and h are stored
@@ -59,7 +59,7 @@ struct Tile {
 constexpr int kTileInterior = 1;
 // The tile lies inside the lattice (else its last columns or rows do not).
 constexpr int kTileWhole = 2;
-// The entry is a run: kRunNodes consecutive nodes in x-fastest order from node
+// The entry is a run: TX * TY consecutive nodes in x-fastest order from node
 // number x0 (y0 unused).  Interior runs hold no node of the first or last row.
 constexpr int kTileRun = 4;
 
@@ -82,18 +82,21 @@ struct InitArgs {
     int shift;  // add eq(new) - eq(current fields in staged planes 5..9) instead of replacing
 };
 
-// Compiled tile shapes (TX x TY nodes, one work-item per node).  Id kTileRuns
-// steps lattices periodic in x with kRunMinNx <= nx <= kRunMaxNx in runs of
-// kRunNodes consecutive nodes (rows of any width then leave no work-item
-// idle) and the other lattices in its TX x TY tiles; it is not used with the
-// potential form of the capillary force (those lattices take tiles).
-constexpr int kTileCount = 7;
-constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128, 128};
-constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4, 4};
+// Compiled tile shapes (TX x TY nodes, one work-item per node).  Ids from
+// kTileRuns on step lattices periodic in x with kRunMinNx <= nx <= kRunMaxNx
+// in runs of TX * TY consecutive nodes (rows of any width then leave no
+// work-item idle) and the other lattices in their TX x TY tiles; they are not
+// used with the potential form of the capillary force (those lattices take
+// tiles).
+constexpr int kTileCount = 8;
+constexpr int kTileTX[kTileCount] = {64, 128, 32, 64, 256, 128, 128, 64};
+constexpr int kTileTY[kTileCount] = {4, 2, 8, 8, 1, 4, 4, 4};
 constexpr int kTileRuns = 6;
-constexpr int kRunNodes = 512, kRunMinNx = 64, kRunMaxNx = 256;
+constexpr int kRunMinNx = 64, kRunMaxNx = 256;
+// Nodes per run of tile id (0: not a run id).
+constexpr int run_nodes(int id) { return id >= kTileRuns ? kTileTX[id] * kTileTY[id] : 0; }
 // Tile id whose TX x TY table serves the field and diagnostics kernels.
-constexpr int grid_tile(int id) { return id == kTileRuns ? 5 : id; }
+constexpr int grid_tile(int id) { return id == 6 ? 5 : (id == 7 ? 0 : id); }
 
 // Launchers (lbm_kernels.hip).  `src` is the time level read (0 = A, 1 = B).
 // `variant` selects the step kernel: 0 BGK only; 1 BGK or two relaxation

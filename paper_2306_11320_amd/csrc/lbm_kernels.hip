@@ -796,11 +796,11 @@ __device__ __forceinline__ bool load_any(const Inst<real>& I, const Tile& tl, in
 }
 
 // ---- runs ----
-// A run is kRunNodes consecutive nodes of a lattice in x-fastest order (node
+// A run is RN consecutive nodes of a lattice in x-fastest order (node
 // number n = y nx + x), one per work-item, so rows of any width leave no
 // work-item idle.  Used for lattices periodic in x with
 // kRunMinNx <= nx <= kRunMaxNx.  The patch of a run starting at n0 is the
-// window of node numbers n0 - nx - 1 ... n0 + kRunNodes + nx (window slot
+// window of node numbers n0 - nx - 1 ... n0 + RN + nx (window slot
 // w = m - n0 + nx + 1 for node number m), which holds every neighbour of the
 // run's nodes in the rows below and above.  A neighbour across the periodic x
 // boundary sits nx - 1 or nx + 1 slots away from where it would be without the
@@ -812,9 +812,9 @@ __device__ __forceinline__ bool load_any(const Inst<real>& I, const Tile& tl, in
 // also get slots of their own: a wall's rule is evaluated at the unwrapped
 // coordinate along the wall (a Dirichlet temperature at -1 or nx), as for
 // every other ghost of a tile's ring.
-template <typename real>
+template <typename real, int RN>
 struct RunPatch {
-    static constexpr int NW = kRunNodes + 2 * kRunMaxNx + 8;
+    static constexpr int NW = RN + 2 * kRunMaxNx + 8;
     static constexpr int GLO = NW - 6, GHI = NW - 5;
     static constexpr int CSW = NW - 4, CSE = NW - 3, CNW = NW - 2, CNE = NW - 1;
     real phi[NW];
@@ -826,7 +826,7 @@ struct RunPatch {
 template <typename real, int TX, int TY>
 union StepLDS {
     Patch<real, TX, TY> tile;
-    RunPatch<real> run;
+    RunPatch<real, TX * TY> run;
 };
 
 // Window slot and lattice point of ring entry q of the run from n0 (q in
@@ -834,10 +834,10 @@ union StepLDS {
 // the run, those above it, the two wrap slots, then the four corner ghosts).
 // Returns whether a node of the run may read the entry: EDGE runs read rows
 // -1 .. ny, interior runs rows 0 .. ny - 1 only.
-template <bool EDGE>
+template <bool EDGE, int RN>
 __device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, int& w, int& gx, int& gy)
 {
-    using RP = RunPatch<float>;
+    using RP = RunPatch<float, RN>;
     if (EDGE && q >= 2 * nx + 4) {
         const int k = q - (2 * nx + 4);
         w = RP::CSW + k;
@@ -846,7 +846,7 @@ __device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, i
         return true;
     }
     if (q < 2 * nx + 2) {
-        w = q < nx + 1 ? q : q + kRunNodes;
+        w = q < nx + 1 ? q : q + RN;
         const int m = n0 - nx - 1 + w;
         if (m < -nx) return false;
         gy = (m + nx) / nx - 1;
@@ -869,13 +869,12 @@ __device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, i
     w = RP::GHI;
     gx = nx - 1;
     gy = yl + 1;
-    return yl * nx - n0 >= kRunNodes - nx + 2;
+    return yl * nx - n0 >= RN - nx + 2;
 }
 
 // Plain fill of a run window slot from lattice point (gx, gy) inside the lattice.
 template <typename real>
-__device__ inline void run_load_entry(const Inst<real>& I, int src, RunPatch<real>& R, int w, int gx, int gy,
-                                      real (&rf)[9], real (&rh)[9])
+__device__ inline void run_load_entry(const Inst<real>& I, int src, int gx, int gy, real (&rf)[9], real (&rh)[9])
 {
     const unsigned idx = (unsigned)(gy * I.pitch + gx);
 #pragma unroll
@@ -883,11 +882,10 @@ __device__ inline void run_load_entry(const Inst<real>& I, int src, RunPatch<rea
         rf[k] = ld(src_plane(I, src, kF + k), noff<real>(idx));
         rh[k] = ld(src_plane(I, src, kH + k), noff<real>(idx));
     }
-    (void)R; (void)w;
 }
 
-template <typename real>
-__device__ inline void run_store_entry(RunPatch<real>& R, const Inst<real>& I, int w, const real (&rf)[9],
+template <typename real, int RN>
+__device__ inline void run_store_entry(RunPatch<real, RN>& R, const Inst<real>& I, int w, const real (&rf)[9],
                                        const real (&rh)[9])
 {
     real sf = 0, sh = 0;
@@ -905,10 +903,10 @@ __device__ inline void run_store_entry(RunPatch<real>& R, const Inst<real>& I, i
 
 // Loads the work-item's own node of the run from n0 and fills the window.
 // Returns whether the node lies in the lattice; (x, y) its coordinates.  In
-// interior runs the first kRunNodes ring entries go one per work-item and
-// their loads are issued together with the node's own.
-template <typename real, bool EDGE>
-__device__ inline bool load_run(const Inst<real>& I, int src, RunPatch<real>& R, int n0, int& x, int& y,
+// interior runs the first RN ring entries go one per work-item and their
+// loads are issued together with the node's own.
+template <typename real, bool EDGE, int RN>
+__device__ inline bool load_run(const Inst<real>& I, int src, RunPatch<real, RN>& R, int n0, int& x, int& y,
                                 real (&f)[9], real (&g)[9], real (&h)[9], real& jpx, real& jpy)
 {
     const int nx = I.nx, ny = I.ny, nn = nx * ny;
@@ -919,13 +917,13 @@ __device__ inline bool load_run(const Inst<real>& I, int src, RunPatch<real>& R,
     x = n - y * nx;
     const int c = t + nx + 1;
     const int nring = 2 * nx + (EDGE ? 8 : 4);
-    const int last = (n0 + kRunNodes < nn ? n0 + kRunNodes : nn) - 1;
+    const int last = (n0 + RN < nn ? n0 + RN : nn) - 1;
     const int yl = last / nx;
 
     int rw = 0, rgx = 0, rgy = 0;
-    const bool ring = !EDGE && t < nring && run_ring<false>(t, n0, nx, ny, yl, rw, rgx, rgy);
+    const bool ring = !EDGE && t < nring && run_ring<false, RN>(t, n0, nx, ny, yl, rw, rgx, rgy);
     real rf[9], rh[9];
-    if (ring) run_load_entry(I, src, R, rw, rgx, rgy, rf, rh);
+    if (ring) run_load_entry(I, src, rgx, rgy, rf, rh);
     if (inside) {
         const unsigned idx = (unsigned)(y * I.pitch + x);
         real sf = 0, sh = 0;
@@ -952,14 +950,14 @@ __device__ inline bool load_run(const Inst<real>& I, int src, RunPatch<real>& R,
         fill_entry<real, true>(I, src, R, c, x, y);
     }
     if (ring) run_store_entry(R, I, rw, rf, rh);
-    for (int q = EDGE ? t : t + kRunNodes; q < nring; q += kRunNodes) {
+    for (int q = EDGE ? t : t + RN; q < nring; q += RN) {
         int w, gx, gy;
-        if (!run_ring<EDGE>(q, n0, nx, ny, yl, w, gx, gy)) continue;
+        if (!run_ring<EDGE, RN>(q, n0, nx, ny, yl, w, gx, gy)) continue;
         if (EDGE) {
             fill_entry<real, true>(I, src, R, w, gx, gy);
         } else {
             real qf[9], qh[9];
-            run_load_entry(I, src, R, w, gx, gy, qf, qh);
+            run_load_entry(I, src, gx, gy, qf, qh);
             run_store_entry(R, I, w, qf, qh);
         }
     }
@@ -988,13 +986,13 @@ __device__ inline void run_pad(const Inst<real>& I, int dst, int x, int y)
     st(to_global(I.jbase[1]), own * (unsigned)sizeof(real), real(0));
 }
 
-template <typename real, bool EDGE, bool TRT>
-__device__ __forceinline__ void run_step(const Inst<real>& I, int n0, int src, RunPatch<real>& R)
+template <typename real, bool EDGE, bool TRT, int RN>
+__device__ __forceinline__ void run_step(const Inst<real>& I, int n0, int src, RunPatch<real, RN>& R)
 {
-    using RP = RunPatch<real>;
+    using RP = RunPatch<real, RN>;
     real f[9], g[9], h[9], jpx = 0, jpy = 0;
     int x, y;
-    const bool inside = load_run<real, EDGE>(I, src, R, n0, x, y, f, g, h, jpx, jpy);
+    const bool inside = load_run<real, EDGE, RN>(I, src, R, n0, x, y, f, g, h, jpx, jpy);
     if (!inside) return;
     const int nx = I.nx, t = threadIdx.x, c = t + nx + 1;
     const bool xl = x == 0, xr = x == nx - 1;
@@ -1007,18 +1005,18 @@ __device__ __forceinline__ void run_step(const Inst<real>& I, int n0, int src, R
     nb.o[3] = xl ? nx - 1 : -1;
     nb.o[4] = -nx;
     nb.o[5] = xr ? (top ? RP::CNE - c : 1) : nx + 1;
-    nb.o[6] = xl ? (top ? RP::CNW - c : (t < kRunNodes - nx + 2 ? 2 * nx - 1 : RP::GHI - c)) : nx - 1;
+    nb.o[6] = xl ? (top ? RP::CNW - c : (t < RN - nx + 2 ? 2 * nx - 1 : RP::GHI - c)) : nx - 1;
     nb.o[7] = xl ? (bot ? RP::CSW - c : -1) : -nx - 1;
     nb.o[8] = xr ? (bot ? RP::CSE - c : (t >= nx - 2 ? 1 - 2 * nx : RP::GLO - c)) : 1 - nx;
     run_pad(I, src ^ 1, x, y);
     node_update<real, EDGE, TRT, false>(I, R, nb, nullptr, x, y, c, src ^ 1, f, g, h, jpx, jpy);
 }
 
-template <typename real, bool TRT>
-__device__ __forceinline__ void run_any(const Inst<real>& I, const Tile& tl, int src, RunPatch<real>& R)
+template <typename real, bool TRT, int RN>
+__device__ __forceinline__ void run_any(const Inst<real>& I, const Tile& tl, int src, RunPatch<real, RN>& R)
 {
-    if (tl.flags & kTileInterior) run_step<real, false, TRT>(I, tl.x0, src, R);
-    else run_step<real, true, TRT>(I, tl.x0, src, R);
+    if (tl.flags & kTileInterior) run_step<real, false, TRT, RN>(I, tl.x0, src, R);
+    else run_step<real, true, TRT, RN>(I, tl.x0, src, R);
 }
 
 // Workgroup -> contiguous run of tiles.  Workgroups are dealt round-robin to
@@ -1038,14 +1036,14 @@ __device__ inline void my_tiles(int ntiles, int& t0, int& t1)
 // VAR 1: some lattice uses two relaxation times; VAR 2: some lattice uses the
 // potential form of the capillary force (extra LDS, a second ring of phi).
 // Separate kernels, so that the BGK-only kernel keeps its own register budget.
-// RUNS: the table may also hold runs (kTileRun entries; TX * TY == kRunNodes,
-// BGK or two relaxation times only); tile and run patches share the LDS.
+// RUNS: the table may also hold runs of TX * TY nodes (kTileRun entries; BGK
+// or two relaxation times only); tile and run patches share the LDS.
 template <typename real, int TX, int TY, int VAR, bool RUNS = false>
 __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ insts, const Tile* __restrict__ tiles,
                                                   int ntiles, int src)
 {
     constexpr bool ANY_TRT = VAR >= 1;
-    static_assert(!RUNS || (TX * TY == kRunNodes && VAR < 2), "runs: one node per work-item, no potential form");
+    static_assert(!RUNS || VAR < 2, "runs: no potential form");
     using LDS = typename std::conditional<RUNS, StepLDS<real, TX, TY>, Patch<real, TX, TY>>::type;
     __shared__ LDS U;
     int t0, t1;
@@ -1068,8 +1066,8 @@ __global__ __launch_bounds__(TX* TY) void k_step(const Inst<real>* __restrict__ 
             else tile_pot<real, TX, TY, true>(I, tl, src, S, Q);
         } else if (RUNS && (tl.flags & kTileRun)) {
             if constexpr (RUNS) {
-                if (!ANY_TRT || I.collision == 0) run_any<real, false>(I, tl, src, U.run);
-                else run_any<real, true>(I, tl, src, U.run);
+                if (!ANY_TRT || I.collision == 0) run_any<real, false, TX * TY>(I, tl, src, U.run);
+                else run_any<real, true, TX * TY>(I, tl, src, U.run);
             }
         } else {
             if (!ANY_TRT || I.collision == 0) tile_any<real, TX, TY, false>(I, tl, src, S);
@@ -1403,18 +1401,21 @@ static hipError_t diag_t(const void* insts, const Tile* tiles, int ntiles, int s
     case 5: return CALL(128, 4);                     \
     default: return hipErrorInvalidValue;            \
     }
-static_assert(kTileTX[kTileRuns] * kTileTY[kTileRuns] == kRunNodes && kTileTX[kTileRuns] == 128 &&
-                  kTileTY[kTileRuns] == 4 && grid_tile(kTileRuns) == 5,
-              "the run kernel is the 128 x 4 kernel");
+static_assert(kTileCount == 8 && kTileTX[6] == 128 && kTileTY[6] == 4 && grid_tile(6) == 5 && kTileTX[7] == 64 &&
+                  kTileTY[7] == 4 && grid_tile(7) == 0,
+              "runs of 512 nodes take the 128 x 4 kernel, runs of 256 the 64 x 4 kernel");
 
 hipError_t launch_step(int prec, int tile, const void* insts, const Tile* tiles, int ntiles, int grid, int src,
                        int variant, hipStream_t s)
 {
 #define STEP64(a, b) step_t<double, a, b>(insts, tiles, ntiles, grid, src, variant, s)
 #define STEP32(a, b) step_t<float, a, b>(insts, tiles, ntiles, grid, src, variant, s)
-    if (tile == kTileRuns)
+    if (tile == 6)
         return prec == 0 ? step_t<double, 128, 4, true>(insts, tiles, ntiles, grid, src, variant, s)
                          : step_t<float, 128, 4, true>(insts, tiles, ntiles, grid, src, variant, s);
+    if (tile == 7)
+        return prec == 0 ? step_t<double, 64, 4, true>(insts, tiles, ntiles, grid, src, variant, s)
+                         : step_t<float, 64, 4, true>(insts, tiles, ntiles, grid, src, variant, s);
     if (prec == 0) { LBM_TILE_SWITCH(tile, STEP64) }
     LBM_TILE_SWITCH(tile, STEP32)
 #undef STEP64
@@ -1434,9 +1435,12 @@ hipError_t step_occupancy(int prec, int tile, int variant, int* blocks_per_cu)
 {
 #define O64(a, b) occ_t<double, a, b>(blocks_per_cu, variant)
 #define O32(a, b) occ_t<float, a, b>(blocks_per_cu, variant)
-    if (tile == kTileRuns)
+    if (tile == 6)
         return prec == 0 ? occ_t<double, 128, 4, true>(blocks_per_cu, variant)
                          : occ_t<float, 128, 4, true>(blocks_per_cu, variant);
+    if (tile == 7)
+        return prec == 0 ? occ_t<double, 64, 4, true>(blocks_per_cu, variant)
+                         : occ_t<float, 64, 4, true>(blocks_per_cu, variant);
     if (prec == 0) { LBM_TILE_SWITCH(tile, O64) }
     LBM_TILE_SWITCH(tile, O32)
 #undef O64

@@ -397,7 +397,7 @@ class Lattice:
 
 
 def tile_shapes() -> list[tuple[int, int]]:
-    """(TX, TY) of every tile id; (512, 0) marks runs of 512 consecutive nodes."""
+    """(TX, TY) of every tile id; (n, 0) marks runs of n consecutive nodes."""
     L = lib()
     out = []
     for t in range(L.lbm_tile_count()):

@@ -1,5 +1,5 @@
-"""Runs: the tile id that steps lattices periodic in x with 64 <= nx <= 256 in
-runs of 512 consecutive nodes (x-fastest order), one workgroup per run.
+"""Runs: the tile ids that step lattices periodic in x with 64 <= nx <= 256 in
+runs of 512 or 256 consecutive nodes (x-fastest order), one workgroup per run.
 
 The per-node arithmetic is that of the tiles, so the state after any number
 of steps is bitwise the same as with the TX x TY tiles; checked from a
@@ -28,10 +28,10 @@ Y_SIDES = [(P, P), (WT, WT), (WA, WT), (IN, OUT)]
 WIDTHS = [(64, 9), (97, 23), (130, 40), (221, 31), (256, 12)]
 
 
-def _runs_id():
+def _run_ids():
     ids = [t for t, (_, ty) in enumerate(lbm.tile_shapes()) if ty == 0]
-    assert len(ids) == 1
-    return ids[0]
+    assert sorted(lbm.tile_shapes()[t][0] for t in ids) == [256, 512]
+    return ids
 
 
 def _perturbed(cfg, f0, prec, seed):
@@ -67,7 +67,8 @@ def test_runs_bitwise_vs_tiles(prec, ysides, shape):
     p = getattr(lbm, prec)
     st = _perturbed(cfg, f0, p, seed=nx)
     ref = _after(cfg, f0, p, 5, st, 13)
-    _same(_after(cfg, f0, p, _runs_id(), st, 13), ref, "runs vs 128x4")
+    for t in _run_ids():
+        _same(_after(cfg, f0, p, t, st, 13), ref, f"{lbm.tile_name(t)} vs 128x4")
     _same(_after(cfg, f0, p, 0, st, 13), ref, "64x4 vs 128x4")
 
 
@@ -82,7 +83,9 @@ def test_runs_bitwise_variants(variant):
     announce("runs_bitwise_variants", variant)
     for prec in (lbm.FP64, lbm.FP32_DEV):
         st = _perturbed(cfg, f0, prec, seed=5)
-        _same(_after(cfg, f0, prec, _runs_id(), st, 11), _after(cfg, f0, prec, 5, st, 11), variant)
+        ref = _after(cfg, f0, prec, 5, st, 11)
+        for t in _run_ids():
+            _same(_after(cfg, f0, prec, t, st, 11), ref, f"{variant}, {lbm.tile_name(t)}")
 
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32_DEV"])
@@ -94,16 +97,20 @@ def test_runs_batched_mixed(prec):
              wl.tiny(64, 17, bc=wl.ALL_BCS[0], seed=5)]
     announce("runs_batched_mixed", prec)
     p = getattr(lbm, prec)
-    b = lbm.Lattice.batch(items, p)
-    b.set_tile(_runs_id())
-    b.step(14)
-    for k, (cfg, f0) in enumerate(items):
+    refs = []
+    for cfg, f0 in items:
         lat = lbm.Lattice(cfg, f0, p)
         lat.set_tile(5)
         lat.step(14)
-        _same(b.get_state(k), lat.get_state(), f"lattice {k}")
+        refs.append(lat.get_state())
         lat.close()
-    b.close()
+    for t in _run_ids():
+        b = lbm.Lattice.batch(items, p)
+        b.set_tile(t)
+        b.step(14)
+        for k in range(len(items)):
+            _same(b.get_state(k), refs[k], f"{lbm.tile_name(t)}, lattice {k}")
+        b.close()
 
 
 @pytest.mark.parametrize("bcs", wl.ALL_BCS[:3], ids=lambda b: "bc" + "".join(map(str, b)))
@@ -121,8 +128,9 @@ def test_runs_one_step_fp64_vs_oracle(bcs, shape, grad_mode):
     o.set_state(**st, step=0)
     o.step(1)
     ref = o.get_state()
-    got = _after(cfg, f0, lbm.FP64, _runs_id(), st, 1)
-    for fam in ("f", "g", "h", "jprev"):
-        scale = max(np.abs(ref[fam]).max(), 1e-300)
-        err = np.abs(got[fam] - ref[fam]).max() / scale
-        assert err <= 2e-13, f"{fam}: max rel diff {err:.3e}"
+    for t in _run_ids():
+        got = _after(cfg, f0, lbm.FP64, t, st, 1)
+        for fam in ("f", "g", "h", "jprev"):
+            scale = max(np.abs(ref[fam]).max(), 1e-300)
+            err = np.abs(got[fam] - ref[fam]).max() / scale
+            assert err <= 2e-13, f"{lbm.tile_name(t)}, {fam}: max rel diff {err:.3e}"
