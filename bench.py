@@ -10,6 +10,7 @@ single-GPU configuration: 64 droplet-migration lattices of uneven size
 together by one persistent launch per step in FP32 deviation storage, tiles
 chosen by the autotuner.  The same JSON line also carries:
 * the batched launch against the same 64 lattices advanced one after another;
+* the same 64 lattices in FP64 (4.7 GB);
 * the two-bubble channel of Sec. 4.3 (512 x 2048) in FP64 (470 MB, streamed
   from HBM) and FP32 (235 MB, at the edge of the 256 MB Infinity Cache);
 * the 256 x 1024 droplet (cache-resident: 59 MB FP32, 117 MB FP64);
@@ -18,8 +19,9 @@ chosen by the autotuner.  The same JSON line also carries:
 * the learned surrogate against the plain FP32 lattice update;
 * the oracle on the host cores, all cores and one thread.
 Working-set bytes are reported next to every number.  --only times just the
-named workload and precision (profiling runs).  Only one GPU is used; --gpus
-above 1 is refused.
+named workload and precision (profiling runs).  Every timed workload takes
+the autotuner's tile (and, for batches, grid) choice.  Only one GPU is used;
+--gpus above 1 is refused.
 """
 from __future__ import annotations
 
@@ -108,7 +110,9 @@ def time_gpu(items, prec, steps, warmup, tile=None, autotune=False, tune_cache=N
     if tile is not None:
         lat.set_tile(tile)
     elif autotune:
-        tuned = lat.autotune(steps_per_trial=max(2, min(50, warmup // 20 or 2)), cache=tune_cache)
+        # single lattices step in ~10-120 us: 50 steps a trial keep launch noise out of the choice
+        tuned = lat.autotune(steps_per_trial=50 if len(items) == 1 else max(2, min(50, warmup // 20 or 2)),
+                             cache=tune_cache)
     lat.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -138,7 +142,7 @@ def lbm_leg(name, prec_name, steps, warmup, tile=None, potential=False, tune_cac
         desc["force_form"] = "potential"
     prec = lbm.FP32_DEV if prec_name == "fp32" else lbm.FP64
     log(f"{desc['workload']}: {prec_name}, {steps} steps")
-    r = time_gpu(items, prec, steps, warmup, tile, autotune=len(items) > 1 and tile is None, tune_cache=tune_cache)
+    r = time_gpu(items, prec, steps, warmup, tile, autotune=tile is None, tune_cache=tune_cache)
     if not r["finite"]:
         raise SystemExit(f"{desc['workload']} {prec_name}: non-finite state after the timed steps")
     word = 4 if prec_name == "fp32" else 8
@@ -158,12 +162,14 @@ def lbm_leg(name, prec_name, steps, warmup, tile=None, potential=False, tune_cac
 
 def time_sequential(items, prec, steps, warmup):
     """The lattices of a batch advanced one after another, each by the
-    single-lattice kernel (one launch per step): the baseline of batching."""
+    single-lattice kernel (one launch per step) with the autotuner's choice
+    for that lattice: the baseline of batching."""
     import torch
     from paper_2306_11320_amd import lbm
     total_ms = 0.0
     for cfg, f0 in items:
         lat = lbm.Lattice(cfg, f0, prec)
+        lat.autotune(steps_per_trial=50)
         lat.step(warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -364,7 +370,8 @@ def main():
                               "speedup_over_sequential": round(seq_ms / head["ms_per_step"], 3),
                               "error": "bitwise equal to the sequential runs (tested)"}
         extra = []
-        for name, prec in (("bubbles", "fp64"), ("bubbles", "fp32"), ("droplet", "fp32"), ("droplet", "fp64")):
+        for name, prec in (("sweep", "fp64"), ("bubbles", "fp64"), ("bubbles", "fp32"), ("droplet", "fp32"),
+                           ("droplet", "fp64")):
             if (name, prec) != (args.workload, args.precision):
                 extra.append((name, prec))
         out["other_workloads"] = []
@@ -375,8 +382,9 @@ def main():
         if not args.no_error:
             log("errors against the FP64 oracle (200-step windows)")
             out["oracle_error"] = {f"{args.workload}_{args.precision}": oracle_error(args.workload, args.precision)}
-            for name, prec in (("bubbles", "fp64"), ("bubbles", "fp32")):
-                out["oracle_error"][f"{name}_{prec}"] = oracle_error(name, prec)
+            for name, prec in (("sweep", "fp64"), ("bubbles", "fp64"), ("bubbles", "fp32")):
+                if (name, prec) != (args.workload, args.precision):
+                    out["oracle_error"][f"{name}_{prec}"] = oracle_error(name, prec)
         if args.surrogate > 0:
             log("surrogate")
             out["surrogate"] = surrogate_leg(args.surrogate)

@@ -306,12 +306,16 @@ int lbm_set_grid(lbm_ctx* c, int workgroups);
 int lbm_get_grid(const lbm_ctx* c);
 
 /*
- * Tile autotuner: times `steps_per_trial` steps with every compiled tile shape
- * (and, for a batched context, a persistent grid of one and two resident waves
- * of workgroups and one workgroup per tile) with HIP events on the context's
- * stream, then keeps the fastest.  Tile shape and grid change only the launch,
- * never the per-node arithmetic, so the trial steps are ordinary steps: the
- * lattices advance by (trials x (steps_per_trial + 1)) steps.  Synchronizes.
+ * Tile autotuner: times G = steps_per_trial rounded up to even steps, one
+ * replay of a captured graph, with every compiled tile shape (the run ids only
+ * if some lattice of the context is stepped in runs; and, for a batched
+ * context, a persistent grid of one and two resident waves of workgroups and
+ * one workgroup per tile) with HIP events on the context's stream, after an
+ * untimed replay of the same graph, then keeps the fastest.  Tile shape and
+ * grid change only the launch, never the per-node arithmetic, so the trial
+ * steps are ordinary steps: the lattices advance by max(G, 8) warm-up steps
+ * plus 2 G steps per trial (and one step where the count is odd).
+ * Synchronizes.
  * Outputs may be NULL.  Errors: LBM_EINVAL, LBM_EHIP.
  */
 int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid, float* best_ms_per_step);

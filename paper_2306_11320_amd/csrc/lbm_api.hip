@@ -230,6 +230,9 @@ struct lbm_ctx {
     // step kernel: 0 BGK only; 1 some lattice relaxes with two relaxation
     // times; 2 some lattice uses the potential form of the capillary force
     int variant = 0;
+    // some lattice is stepped in runs by the run tile ids (else those ids
+    // repeat the tiles of their TX x TY shape)
+    bool has_runs = false;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -353,6 +356,7 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     c->ws_bytes = ws_bytes;
     c->params.assign(ps, ps + n);
     c->variant = step_variant(ps, n);
+    for (int k = 0; k < n; ++k) c->has_runs = c->has_runs || runs_for(ps[k], c->variant);
     c->lay = lay;
     c->grid = n > 1 ? -1 : 0;  // batched: persistent grid sized at the first step
     c->d_insts = c->ws + off_insts;
@@ -907,13 +911,25 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // Each trial replays a captured graph of G steps, as lbm_step does: the
+    // graph of a configuration is captured and replayed once untimed, then
+    // replayed once timed (plain launches would time the launch path of
+    // small lattices rather than their kernels).
     const int saved_graph = c->graph_steps;
+    const int G = steps_per_trial + (steps_per_trial & 1);
     drop_graph(c);
-    c->graph_steps = 0;  // plain launches: every trial sees the same launch path
+    c->graph_steps = G;
     float best = 1e30f;
     int bt = c->tile, bg = c->grid;
-    int rc = LBM_OK;
+    // untimed steps first: the first candidate must not be timed on a cold
+    // device (clocks and caches)
+    int rc = lbm_step(c, G > 8 ? G : 8);
+    if (rc == LBM_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = fail(LBM_EHIP, "autotune warm-up: %s", hipGetErrorString(e));
+    }
     for (int t = 0; t < lbm::kTileCount && rc == LBM_OK; ++t) {
+        if (lbm::run_nodes(t) && !c->has_runs) continue;
         int grids[3] = {0, 0, 0}, ng = 1;
         if (c->n > 1) {
             int per_cu = 1;
@@ -927,11 +943,13 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
         for (int q = 0; q < ng && rc == LBM_OK; ++q) {
             c->tile = t;
             c->grid = grids[q];
-            // one untimed step in this configuration, then the timed trial
-            rc = lbm_step(c, 1);
+            drop_graph(c);
+            // an even step count starts a graph; the untimed replay captures it
+            if (c->step & 1) rc = lbm_step(c, 1);
+            if (rc == LBM_OK) rc = lbm_step(c, G);
             if (rc) break;
             hipError_t e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess) rc = lbm_step(c, steps_per_trial);
+            if (e == hipSuccess) rc = lbm_step(c, G);
             if (rc) break;
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -941,7 +959,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
                 rc = fail(LBM_EHIP, "autotune timing: %s", hipGetErrorString(e));
                 break;
             }
-            ms /= (float)steps_per_trial;
+            ms /= (float)G;
             if (ms < best) {
                 best = ms;
                 bt = t;
@@ -951,6 +969,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, int* best_tile, int* best_grid
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    drop_graph(c);
     c->tile = bt;
     c->grid = bg;
     c->graph_steps = saved_graph;

@@ -134,3 +134,15 @@ def test_runs_one_step_fp64_vs_oracle(bcs, shape, grad_mode):
             scale = max(np.abs(ref[fam]).max(), 1e-300)
             err = np.abs(got[fam] - ref[fam]).max() / scale
             assert err <= 2e-13, f"{lbm.tile_name(t)}, {fam}: max rel diff {err:.3e}"
+
+
+def test_autotune_skips_runs_without_run_lattices():
+    """A context with no lattice that runs can step (walls in x; nx > 256)
+    never times, and so never keeps, a run id; with a run lattice it may."""
+    items = [wl.tiny(70, 90, bc=wl.ALL_BCS[4], seed=2), wl.tiny(300, 20, bc=wl.ALL_BCS[0], seed=3)]
+    announce("autotune_skips_runs")
+    for _ in range(2):
+        b = lbm.Lattice.batch(items, lbm.FP32_DEV)
+        res = b.autotune(steps_per_trial=2)
+        assert res["tile"] not in _run_ids(), res
+        b.close()
