@@ -244,12 +244,15 @@ int lbm_set_state(lbm_ctx* c, int instance, const double* f, const double* g, co
                   const double* jprev, int64_t step);
 
 /* Size of a raw checkpoint: the native populations, jprev, the step counter and
- * a hash of the parameters, so that a resumed run is bitwise identical. */
+ * a hash of the parameters, so that a resumed run is bitwise identical.  The
+ * populations keep the library's storage layout, which its format tag names
+ * (a checkpoint of another layout is refused). */
 size_t lbm_checkpoint_bytes(const lbm_ctx* c);
 /* Writes the checkpoint into host memory.  Synchronizes the stream. */
 int lbm_checkpoint_save(lbm_ctx* c, void* host_buf, size_t bytes);
 /* Restores a checkpoint written by a context with identical parameters;
- * LBM_EINVAL if the size or the parameter hash differ.  Synchronizes. */
+ * LBM_EINVAL if the size, the format tag or the parameter hash differ.
+ * Synchronizes. */
 int lbm_checkpoint_load(lbm_ctx* c, const void* host_buf, size_t bytes);
 
 /* ---- batched lattices (many parameter-sweep instances in one launch) ---- */

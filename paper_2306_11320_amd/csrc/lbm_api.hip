@@ -791,7 +791,7 @@ int lbm_checkpoint_save(lbm_ctx* c, void* host_buf, size_t bytes)
     for (int k = 0; k < c->n; ++k) {
         const Layout& L = c->lay[k];
         CkptHeader hd{};
-        std::memcpy(hd.magic, "LBMCKPT2", 8);
+        std::memcpy(hd.magic, "LBMCKPT3", 8);
         hd.version = LBM_ABI_VERSION;
         hd.prec = c->prec;
         hd.n = c->n;
@@ -823,8 +823,8 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* host_buf, size_t bytes)
     const size_t rsz = real_size(c->prec);
     CkptHeader first{};
     std::memcpy(&first, p, sizeof(first));
-    if (std::memcmp(first.magic, "LBMCKPT2", 8) || first.hash != hsh || first.prec != c->prec || first.n != c->n)
-        return fail(LBM_EINVAL, "checkpoint was written by a context with different parameters");
+    if (std::memcmp(first.magic, "LBMCKPT3", 8) || first.hash != hsh || first.prec != c->prec || first.n != c->n)
+        return fail(LBM_EINVAL, "checkpoint of another format, or written by a context with different parameters");
     const int lvl = (int)(first.step & 1);
     for (int k = 0; k < c->n; ++k) {
         const Layout& L = c->lay[k];

@@ -189,6 +189,15 @@ def test_checkpoint_resume_bitwise():
     for k in ("f", "g", "h", "jprev"):
         assert np.array_equal(sa[k], sb[k]), k
     assert sb["step"] == 71
+    # a checkpoint of another storage layout (format tag) or other parameters is refused
+    bad = bytearray(ck)
+    bad[7] ^= 1
+    with pytest.raises(lbm.LbmError):
+        b.restore(bytes(bad))
+    other = dict(cfg, mobility=cfg["mobility"] * 1.5)
+    c = lbm.Lattice(other, f0, lbm.FP64)
+    with pytest.raises(lbm.LbmError):
+        c.restore(ck)
 
 
 # ---- two-relaxation-time collision -------------------------------------------
