@@ -29,14 +29,51 @@ __device__ inline bf16x8 load8(const bf16* p)
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// max(v, 0) of 8 BF16 values as packed 16-bit integer maxima: a BF16 value
+// with its sign bit set is a negative 16-bit integer and a positive one a
+// positive integer, so the integer maximum with 0 is the ReLU (-0 becomes +0)
+// at four packed instructions instead of eight conversions and selects.
 __device__ inline bf16x8 relu8(bf16x8 v)
 {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (float)v[j] > 0.f ? v[j] : (__bf16)0.f;
-    return v;
+    const s16x8 s = __builtin_bit_cast(s16x8, v);
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(s, (s16x8)(short)0));
 }
 
 __device__ inline float to_f(bf16 v) { return (float)v; }
+
+// Epilogue of one segment: element i of the accumulator is pixel
+// x0 + 4 kh + 8 (i / 4) + i % 4 of the row (offset o_row of its first pixel,
+// channel 0), channel co.  A segment inside the row (every segment of a row
+// whose width is a multiple of 32) stores without per-pixel tests.
+template <bool OUTF32, bool RES, bool MASK>
+__device__ inline void conv_store(const f32x16& acc, float bv, const void* __restrict__ res,
+                                  const bf16* __restrict__ mask, void* __restrict__ out, long long o_row, int x0, int W,
+                                  int kh, int co)
+{
+    const long long o0 = o_row + (4 * kh) * 32 + co;
+    auto one = [&](int i) {
+        const long long idx = o0 + (8 * (i / 4) + (i % 4)) * 32;
+        float v = acc[i] + bv;
+        if (MASK) v = to_f(mask[idx]) > 0.f ? v : 0.f;
+        if (OUTF32) {
+            if (RES) v += static_cast<const float*>(res)[idx];
+            static_cast<float*>(out)[idx] = v;
+        } else {
+            if (RES) v += to_f(static_cast<const bf16*>(res)[idx]);
+            static_cast<bf16*>(out)[idx] = (bf16)v;
+        }
+    };
+    if (x0 + 32 <= W) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) one(i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (x0 + 4 * kh + 8 * (i / 4) + (i % 4) < W) one(i);
+    }
+}
 
 // out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + d dy, x + d dx, ci) W[co][tap][ci] )
 // with dilation d; A = relu(in) if RELU.  Epilogue: + bias[co] (if bias);
@@ -56,7 +93,10 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     const int lane = threadIdx.x % 64;
     const int segs_per_row = (W + 31) / 32;
     const long long nseg = (long long)N * H * segs_per_row;
-    const long long wave0 = (long long)blockIdx.x * 4 + threadIdx.x / 64;
+    // the segment index is the same for every lane of a wave: kept scalar, so
+    // that everything derived from it (row, frame, validity of tap rows) is
+    // scalar too
+    const long long wave0 = (long long)blockIdx.x * 4 + (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const long long nwaves = (long long)gridDim.x * 4;
     const int m = lane % 32, kh = lane / 32;
     // the weight operands of the whole K loop are staged once per workgroup
@@ -81,39 +121,62 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
         const int y = (int)(ny % H), n = (int)(ny / H);
         const int xm = x0 + m < W ? x0 + m : W - 1;
         bf16x8 a[NKB];
+        if constexpr (CIN == 32) {
+            // K block q is tap q / 2, channels 16 (q % 2) + 8 kh ... + 7: the
+            // three tap rows (clamped to the frame) and the three tap columns
+            // (periodic) are computed once per segment
+            const bf16* rowp[3];
+            bool rok[3];
 #pragma unroll
-        for (int q = 0; q < NKB; ++q) {
-            const int kk = q * 16 + 8 * kh;
-            const bool kv = kk < K;
-            const int kc = kv ? kk : 0;
-            const int tap = kc / CIN, ci = kc % CIN;
-            const int yy = y + (tap / 3 - 1) * dil;
-            int xx = xm + (tap % 3 - 1) * dil;  // |offset| <= W, so one wrap suffices
-            xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
-            const bool ok = kv && yy >= 0 && yy < H;
-            const int yc = ok ? yy : y;
-            a[q] = load8(in + (((long long)n * H + yc) * W + xx) * CIN + ci);
-            if (!ok) a[q] = bf16x8{};
-        }
-        f32x16 acc = {};
-#pragma unroll
-        for (int q = 0; q < NKB; ++q)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
-        const long long row = ((long long)n * H + y) * W;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int px = x0 + 8 * (i / 4) + 4 * kh + (i % 4);
-            if (px >= W) continue;
-            const long long idx = (row + px) * 32 + co;
-            float v = acc[i] + bv;
-            if (MASK) v = to_f(mask[idx]) > 0.f ? v : 0.f;
-            if (OUTF32) {
-                if (RES) v += static_cast<const float*>(res)[idx];
-                static_cast<float*>(out)[idx] = v;
-            } else {
-                if (RES) v += to_f(static_cast<const bf16*>(res)[idx]);
-                static_cast<bf16*>(out)[idx] = (bf16)v;
+            for (int r = 0; r < 3; ++r) {
+                const int yy = y + (r - 1) * dil;
+                rok[r] = yy >= 0 && yy < H;
+                rowp[r] = in + ((long long)n * H + (rok[r] ? yy : y)) * W * CIN + 8 * kh;
             }
+            int xc[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int xx = xm + (c - 1) * dil;  // |offset| <= W, so one wrap suffices
+                xc[c] = (xx < 0 ? xx + W : (xx >= W ? xx - W : xx)) * CIN;
+            }
+#pragma unroll
+            for (int q = 0; q < NKB; ++q) {
+                const int tap = q >> 1;
+                a[q] = load8(rowp[tap / 3] + xc[tap % 3] + 16 * (q & 1));
+            }
+            // a tap row outside the frame contributes nothing: its operands
+            // are zeroed (a select on a scalar condition: zeroing under a
+            // branch held 92 VGPRs against 63)
+#pragma unroll
+            for (int q = 0; q < NKB; ++q)
+                if (!rok[(q >> 1) / 3]) a[q] = bf16x8{};
+            f32x16 acc = {};
+#pragma unroll
+            for (int q = 0; q < NKB; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
+            conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh,
+                                          co);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NKB; ++q) {
+                const int kk = q * 16 + 8 * kh;
+                const bool kv = kk < K;
+                const int kc = kv ? kk : 0;
+                const int tap = kc / CIN, ci = kc % CIN;
+                const int yy = y + (tap / 3 - 1) * dil;
+                int xx = xm + (tap % 3 - 1) * dil;  // |offset| <= W, so one wrap suffices
+                xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+                const bool ok = kv && yy >= 0 && yy < H;
+                const int yc = ok ? yy : y;
+                a[q] = load8(in + (((long long)n * H + yc) * W + xx) * CIN + ci);
+                if (!ok) a[q] = bf16x8{};
+            }
+            f32x16 acc = {};
+#pragma unroll
+            for (int q = 0; q < NKB; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
+            conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh,
+                                          co);
         }
     }
 }
