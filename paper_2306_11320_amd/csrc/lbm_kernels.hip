@@ -831,13 +831,14 @@ union StepLDS {
 
 // Window slot and lattice point of ring entry q of the run from n0 (q in
 // [0, 2 nx + 4), and in EDGE runs also [2 nx + 4, 2 nx + 8): the slots below
-// the run, those above it, the two wrap slots, then the four corner ghosts).
-// Returns whether a node of the run may read the entry: EDGE runs read rows
-// -1 .. ny, interior runs rows 0 .. ny - 1 only.
+// the run, those above it, the two wrap slots, then the four corner ghosts);
+// yl is the row of the run's last node.  Returns whether a node of the run may
+// read the entry: EDGE runs read rows -1 .. ny, interior runs rows 0 .. ny - 1
+// only.
 template <bool EDGE, int RN>
-__device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, int& w, int& gx, int& gy)
+__device__ inline bool run_ring(int q, int n0, int nx, int ny, int yl, int& w, int& gx, int& gy)
 {
-    using RP = RunPatch<float, RN>;
+    using RP = RunPatch<float, RN>;  // slot numbers do not depend on the word size
     if (EDGE && q >= 2 * nx + 4) {
         const int k = q - (2 * nx + 4);
         w = RP::CSW + k;
@@ -862,10 +863,9 @@ __device__ inline bool run_ring(int q, int n0, int nx, int ny, int w_hi_first, i
         gy = y0 - 1;
         return x0 >= 2;
     }
-    // (nx - 1, yl + 1): north-west neighbour of the last node with x = 0 (row
-    // yl of the run's last node), outside the window when that node is among
-    // the last nx - 2 slots of the run
-    const int yl = w_hi_first;
+    // (nx - 1, yl + 1): north-west neighbour of the last node with x = 0 (in
+    // row yl), outside the window when that node is among the last nx - 2
+    // slots of the run
     w = RP::GHI;
     gx = nx - 1;
     gy = yl + 1;
@@ -996,7 +996,7 @@ __device__ __forceinline__ void run_step(const Inst<real>& I, int n0, int src, R
     if (!inside) return;
     const int nx = I.nx, t = threadIdx.x, c = t + nx + 1;
     const bool xl = x == 0, xr = x == nx - 1;
-    // corner ghosts (EDGE runs only hold nodes of the first or last row)
+    // corner ghosts (only EDGE runs hold nodes of the first or last row)
     const bool bot = EDGE && y == 0, top = EDGE && y == I.ny - 1;
     RunNb nb;
     nb.o[0] = 0;
