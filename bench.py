@@ -197,10 +197,11 @@ def _field_errors(got: dict, ref: dict, T0: float) -> dict:
     return out
 
 
-def oracle_error(name: str, prec_name: str, steps: int = 200, lattices=(0, 1, 2)):
+def oracle_error(name: str, prec_name: str, steps: int = 200, lattices=(0, 1, 2), tile=None):
     """The GPU path against the FP64 oracle on the timed workload: both take
     `steps` steps from the initial state (for the sweep, lattices `lattices`
-    of the batch, stepped inside the batch), then the fields are compared."""
+    of the batch, stepped inside the batch), then the fields are compared.
+    `tile`: the tile id the timed run used (else the default)."""
     import oracle
     from paper_2306_11320_amd import lbm
     items, _ = make_workload(name)
@@ -211,6 +212,8 @@ def oracle_error(name: str, prec_name: str, steps: int = 200, lattices=(0, 1, 2)
     else:
         lat = lbm.Lattice(items[0][0], items[0][1], prec)
         which = [0]
+    if tile is not None:
+        lat.set_tile(tile)
     lat.step(steps)
     worst = {}
     for k in which:
@@ -219,8 +222,9 @@ def oracle_error(name: str, prec_name: str, steps: int = 200, lattices=(0, 1, 2)
         o.step(steps)
         e = _field_errors(lat.fields(k), o.fields(), float(cfg.get("T_ref", 0.0)))
         worst = {q: max(worst.get(q, 0.0), v) for q, v in e.items()}
+    lat_tile = lat.tile()
     lat.close()
-    return {"steps": steps, "lattices": which if len(items) > 1 else None,
+    return {"steps": steps, "lattices": which if len(items) > 1 else None, "tile": lbm.tile_name(lat_tile),
             "rel_l2": {k: float(f"{v:.3e}") for k, v in worst.items()}}
 
 
@@ -375,16 +379,21 @@ def main():
             if (name, prec) != (args.workload, args.precision):
                 extra.append((name, prec))
         out["other_workloads"] = []
+        # tile id each timed workload ran with: its error window runs with it too
+        timed_tile = {(args.workload, args.precision): (head.get("autotuned") or {}).get("tile", args.tile)}
         for name, prec in extra:
             leg, _, _ = lbm_leg(name, prec, args.steps, args.warmup, None, args.potential)
             leg["cache_resident"] = leg["working_set_bytes"] <= 256 * 2 ** 20
+            timed_tile[(name, prec)] = (leg.get("autotuned") or {}).get("tile")
             out["other_workloads"].append(leg)
         if not args.no_error:
             log("errors against the FP64 oracle (200-step windows)")
-            out["oracle_error"] = {f"{args.workload}_{args.precision}": oracle_error(args.workload, args.precision)}
-            for name, prec in (("sweep", "fp64"), ("bubbles", "fp64"), ("bubbles", "fp32")):
-                if (name, prec) != (args.workload, args.precision):
-                    out["oracle_error"][f"{name}_{prec}"] = oracle_error(name, prec)
+            out["oracle_error"] = {}
+            for name, prec in ((args.workload, args.precision), ("sweep", "fp64"), ("bubbles", "fp64"),
+                               ("bubbles", "fp32")):
+                key = f"{name}_{prec}"
+                if key not in out["oracle_error"]:
+                    out["oracle_error"][key] = oracle_error(name, prec, tile=timed_tile.get((name, prec)))
         if args.surrogate > 0:
             log("surrogate")
             out["surrogate"] = surrogate_leg(args.surrogate)
