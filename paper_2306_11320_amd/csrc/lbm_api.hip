@@ -51,6 +51,8 @@ struct Layout {
     long long plane;        // elements per plane
     size_t pop_off[2];      // byte offsets of time levels A and B
     size_t jprev_off;
+    size_t twall_off;       // byte offset of the wall-temperature tables
+    int tw_stride;          // entries per side
     int tile_off[lbm::kTileCount], tile_cnt[lbm::kTileCount];
 };
 
@@ -138,6 +140,11 @@ Layout make_layout(const lbm_params& p, size_t rsz, int variant, size_t& cursor)
     cursor = align_up(cursor + level, kAlign);
     L.jprev_off = cursor;
     cursor = align_up(cursor + 2 * (size_t)L.plane * rsz, kAlign);
+    // wall temperatures at s = -kTwPad/2 ... max(nx, ny) + kTwPad/2 - 1/2 in
+    // steps of 1/2, for each of the four sides
+    L.tw_stride = 2 * (L.nx > L.ny ? L.nx : L.ny) + 2 * lbm::kTwPad;
+    L.twall_off = cursor;
+    cursor = align_up(cursor + 4 * (size_t)L.tw_stride * rsz, kAlign);
     return L;
 }
 
@@ -194,16 +201,31 @@ lbm::Inst<real> make_inst(const lbm_params& p, const Layout& L, char* ws)
     I.fac_phi = (real)(1.0 - 0.5 / tau_phi);
     I.Gx = (real)p.Gx;
     I.Gy = (real)p.Gy;
-    for (int s = 0; s < 4; ++s) {
-        I.tw_mean[s] = (real)(p.Tw_mean[s] - T0);
-        I.tw_amp[s] = (real)p.Tw_amp[s];
-        I.tw_k[s] = (real)p.Tw_k[s];
-        I.tw_slope[s] = (real)p.Tw_slope[s];
-    }
+    I.twall = reinterpret_cast<const real*>(ws + L.twall_off);
+    I.tw_stride = L.tw_stride;
     I.u_in = (real)p.u_in_mean;
     I.phi_in_d = (real)(p.phi_in - phi0);
     I.T_in_d = (real)(p.T_in - T0);
     return I;
+}
+
+// Wall temperatures relative to T0 at s = (j - kTwPad) / 2 along each side,
+// T_w(s) = Tw_mean + Tw_amp cos(Tw_k s) + Tw_slope s, for the boundary rules
+// of the step kernel; copied into the lattice's table (the stream is
+// synchronized before the host copy is freed).
+template <typename real>
+hipError_t put_wall_table(const lbm_params& p, const Layout& L, char* ws, hipStream_t s)
+{
+    std::vector<real> t(4 * (size_t)L.tw_stride);
+    for (int side = 0; side < 4; ++side)
+        for (int j = 0; j < L.tw_stride; ++j) {
+            const double x = 0.5 * (j - lbm::kTwPad);
+            const double Tw = p.Tw_mean[side] + p.Tw_amp[side] * std::cos(p.Tw_k[side] * x) + p.Tw_slope[side] * x;
+            t[(size_t)side * L.tw_stride + j] = (real)(Tw - p.T0_dev);
+        }
+    hipError_t e = hipMemcpyAsync(ws + L.twall_off, t.data(), t.size() * sizeof(real), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
 }
 
 uint64_t params_hash(const std::vector<lbm_params>& ps)
@@ -385,6 +407,11 @@ int init_common(int n, const lbm_params* ps, const double* const* phi0, const do
     };
     hipError_t e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), c->h_insts.size(), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return bail(fail(LBM_EHIP, "copy of lattice constants: %s", hipGetErrorString(e)));
+    for (int k = 0; k < n; ++k) {
+        e = c->prec == LBM_FP64 ? put_wall_table<double>(ps[k], lay[k], c->ws, c->stream)
+                                : put_wall_table<float>(ps[k], lay[k], c->ws, c->stream);
+        if (e != hipSuccess) return bail(fail(LBM_EHIP, "copy of wall temperatures: %s", hipGetErrorString(e)));
+    }
     // tile tables for every compiled shape, ordered by lattice then row-major
     // tiles (or runs in node order)
     for (int t = 0; t < lbm::kTileCount; ++t) {

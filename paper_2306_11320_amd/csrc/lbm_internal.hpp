@@ -18,6 +18,8 @@ namespace lbm {
 constexpr int kPlanes = 27;
 constexpr int kBlock = 64;
 constexpr int kF = 0, kG = 9, kH = 18;
+// Entries of a side's wall-temperature table before its point s = 0.
+constexpr int kTwPad = 4;
 // Element index, within a level, of population q of node idx.
 __host__ __device__ constexpr long long pop_index(int q, long long idx)
 {
@@ -47,7 +49,11 @@ struct Inst {
     real W2, pref, inv_W2, inv_s2W;             // W^2, 3 sqrt(2) W / 4, 1/W^2, 1/(sqrt(2) W)
     real inv_tau_phi, fac_phi;                  // 1/tau_phi, 1 - 1/(2 tau_phi)
     real Gx, Gy;
-    real tw_mean[4], tw_amp[4], tw_k[4], tw_slope[4];  // tw_mean relative to T0
+    // Wall temperatures relative to T0 at the points s = j/2 - kTwPad/2 along
+    // each side (nodes and the half-way points between them), j = 0 ..
+    // tw_stride - 1, side after side: tabulated on the host at init
+    const real* twall;
+    int tw_stride;
     real u_in, phi_in_d, T_in_d;                // phi_in - phi0, T_in - T0
 };
 

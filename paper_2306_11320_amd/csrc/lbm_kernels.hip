@@ -115,16 +115,22 @@ struct PotLDS {
 };
 struct NoPot {};
 
-// Wall temperature relative to T0 at coordinate s along `side`.
+// Wall temperature relative to T0 at coordinate s = s2 / 2 along `side` (s2 an
+// integer: nodes and the half-way points between them), from the table the
+// host fills at init with T_w(s) = Tw_mean + Tw_amp cos(Tw_k s) + Tw_slope s.
+// An inline FP64 cosine held ~50 VGPRs in the boundary code of the step kernel
+// (a wave per SIMD).  Points beyond the table (ghosts of patch entries that no
+// stencil reads, in tiles cut by the lattice's end) take its end values.
 template <typename real>
-__device__ inline real wall_T(const Inst<real>& I, int side, real s)
+__device__ inline real wall_T(const Inst<real>& I, int side, int s2)
 {
-    return I.tw_mean[side] + I.tw_amp[side] * cos(I.tw_k[side] * s) + I.tw_slope[side] * s;
+    const int j = min(max(s2 + kTwPad, 0), I.tw_stride - 1);
+    return to_global<const real>(I.twall)[side * I.tw_stride + j];
 }
 
 // Affine ghost rule of one side: ghost = a + sgn * inner (deviation units).
 template <typename real>
-__device__ inline void ghost_rule(const Inst<real>& I, int side, real s, real& aphi, real& sphi, real& aT, real& sT)
+__device__ inline void ghost_rule(const Inst<real>& I, int side, int s2, real& aphi, real& sphi, real& aT, real& sT)
 {
     const int bc = I.bc[side];
     aphi = real(0); sphi = real(1); aT = real(0); sT = real(1);
@@ -132,7 +138,7 @@ __device__ inline void ghost_rule(const Inst<real>& I, int side, real s, real& a
         aphi = real(2) * I.phi_in_d; sphi = real(-1);
         aT = real(2) * I.T_in_d; sT = real(-1);
     } else if (bc == BC_WALL_T) {
-        aT = real(2) * wall_T(I, side, s); sT = real(-1);
+        aT = real(2) * wall_T(I, side, s2); sT = real(-1);
     }
 }
 
@@ -153,7 +159,7 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
             jj = gy < 0 ? gy + ny : gy - ny;
         } else {
             jj = gy < 0 ? -1 - gy : 2 * ny - 1 - gy;
-            ghost_rule(I, side, real(gx), ayp, syp, ayT, syT);
+            ghost_rule(I, side, 2 * gx, ayp, syp, ayT, syT);
             real_node = false;
         }
     }
@@ -164,7 +170,7 @@ __device__ inline bool resolve(const Inst<real>& I, int gx, int gy, int& sx, int
             ii = gx < 0 ? gx + nx : gx - nx;
         } else {
             ii = gx < 0 ? -1 - gx : 2 * nx - 1 - gx;
-            ghost_rule(I, side, real(jj), axp, sxp, axT, sxT);
+            ghost_rule(I, side, 2 * jj, axp, sxp, axT, sxT);
             real_node = false;
         }
     }
@@ -670,17 +676,18 @@ __device__ __forceinline__ void node_update(const Inst<real>& I, const P& S, con
             const int bc = I.bc[side];
             const real w = wgt<real>(k);
             const real cu = real(cx(k)) * m.ux + real(cy(k)) * m.uy;
-            const real s = side < 2 ? real(gj) + real(0.5) * real(cy(k)) : real(gi) + real(0.5) * real(cx(k));
+            // crossing point of the link: s = s2 / 2 along the side
+            const int s2 = side < 2 ? 2 * gj + cy(k) : 2 * gi + cx(k);
             real fb, gb, hb;
             if (bc == BC_WALL_T || bc == BC_WALL_ADIABATIC) {
                 // halfway bounce-back; anti-bounce-back for a Dirichlet temperature
                 fb = fsk;
                 gb = gsk;
-                hb = bc == BC_WALL_T ? -hsk + real(2) * w * wall_T(I, side, s) : hsk;
+                hb = bc == BC_WALL_T ? -hsk + real(2) * w * wall_T(I, side, s2) : hsk;
             } else if (bc == BC_INLET) {
                 // anti-bounce-back for phi and T, moving-wall bounce-back for u
                 const real H = side < 2 ? real(I.ny) : real(I.nx);
-                const real sp = s + real(0.5);
+                const real sp = real(0.5) * real(s2 + 1);
                 const real un = real(6) * I.u_in * sp * (H - sp) / (H * H);
                 const real uix = side == 0 ? un : (side == 1 ? -un : real(0));
                 const real uiy = side == 2 ? un : (side == 3 ? -un : real(0));
