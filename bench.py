@@ -16,7 +16,9 @@ chosen by the autotuner.  The same JSON line also carries:
 * the 256 x 1024 droplet (cache-resident: 59 MB FP32, 117 MB FP64);
 * for each timed workload the error against the FP64 oracle after a 200-step
   window from the initial state (three lattices of the sweep);
-* the learned surrogate against the plain FP32 lattice update;
+* the learned surrogate (trained on 2000 trajectories of the batched-sweep
+  generator) against the plain FP32 lattice update, on 256 x 1024 lattices
+  and on the generator's uneven lattices;
 * the oracle on the host cores, all cores and one thread.
 Working-set bytes are reported next to every number.  --only times just the
 named workload and precision (profiling runs).  Every timed workload takes
@@ -261,7 +263,7 @@ def cpu_baseline(items, budget_s: float = 12.0):
                                "sample": f"{sample}: {n1} steps in {d1:.1f} s on one thread"})
 
 
-def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000, weights: str = "surrogate_k100.npz",
+def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000, weights: str = "surrogate_k100_sweep2000.npz",
                   lattices: str = "256x1024"):
     """Hybrid rollout of a trained surrogate against the plain FP32 lattice
     update: speedup and relative L2 errors over `blocks` blocks of 100 steps,
@@ -395,11 +397,16 @@ def main():
                 if key not in out["oracle_error"]:
                     out["oracle_error"][key] = oracle_error(name, prec, tile=timed_tile.get((name, prec)))
         if args.surrogate > 0:
+            # the network trained on 2000 trajectories of the batched-sweep
+            # generator, on 256 x 1024 lattices and on the generator's own
+            # uneven lattices; beside it the earlier network trained on 64
+            # fixed 256 x 1024 lattices
             log("surrogate")
             out["surrogate"] = surrogate_leg(args.surrogate)
-            log("surrogate trained on 2000 trajectories of the batched-sweep generator")
-            out["surrogate_sweep2000"] = surrogate_leg(2, warm=22000, weights="surrogate_k100_sweep2000.npz",
-                                                       lattices="sweep")
+            log("surrogate on lattices of the batched-sweep generator")
+            out["surrogate_uneven"] = surrogate_leg(2, lattices="sweep")
+            log("surrogate trained on 64 fixed lattices")
+            out["surrogate_fixed64"] = surrogate_leg(2, weights="surrogate_k100.npz")
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(items)

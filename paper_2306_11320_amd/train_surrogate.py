@@ -14,6 +14,13 @@ discarded.  --source fixed: --n-train lattices of --nx x --ny, all pairs held
 in memory, --iters Adam steps.  Both use a cosine learning-rate decay.
 Evaluation: --n-eval fresh lattices from the same generator (seed
 --eval-seed) warmed up for --warm steps, then --blocks blocks of K steps.
+
+The committed weights: weights/surrogate_k100_sweep2000.npz (the production
+network) from the defaults, i.e. 2000 trajectories, pairs every 500 steps
+from t = 28000 to 36000, 700 Adam steps per batch of 64 lattices (17 min on
+one MI355X); weights/surrogate_k100.npz (the earlier network) from
+--source fixed --t0 20000 --t1 45000 --n-eval 8 --blocks 30.  Each has a
+report beside it with the arguments of its run.
 """
 from __future__ import annotations
 
@@ -54,23 +61,23 @@ def main(argv=None) -> dict:
     ap.add_argument("--n-train", type=int, default=64)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--K", type=int, default=100)
-    ap.add_argument("--t0", type=int, default=20000)
-    ap.add_argument("--t1", type=int, default=45000)
+    ap.add_argument("--t0", type=int, default=28000)
+    ap.add_argument("--t1", type=int, default=36000)
     ap.add_argument("--stride", type=int, default=500)
     ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--crop", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--n-eval", type=int, default=8)
+    ap.add_argument("--n-eval", type=int, default=4)
     ap.add_argument("--eval-seed", type=int, default=55)
     ap.add_argument("--warm", type=int, default=30000)
-    ap.add_argument("--blocks", type=int, default=30)
+    ap.add_argument("--blocks", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--tol-check", type=float, default=0.01)
     ap.add_argument("--source", default="sweep", choices=["sweep", "fixed"])
     ap.add_argument("--n-traj", type=int, default=2000)
     ap.add_argument("--batch-lattices", type=int, default=64)
-    ap.add_argument("--iters-per-batch", type=int, default=500)
+    ap.add_argument("--iters-per-batch", type=int, default=700)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--checkpoint", default=None, help="save the weights here after every 4 batches")
     ap.add_argument("--init", default=None, help="start from these weights (and their kappa) instead of random ones")

@@ -359,7 +359,8 @@ def test_hybrid_bookkeeping():
 
 
 def test_trained_network_gain():
-    """The committed trained network against the plain FP32 lattice update on
+    """The earlier network, trained on 64 fixed 256 x 1024 lattices
+    (weights/surrogate_k100.npz), against the plain FP32 lattice update on
     two fresh droplet lattices (sweep parameters, seed 55), 10 blocks of 100
     steps after 30000 steps of warm-up: the hybrid is at least twice as fast
     and needs no fallback; every field stays within 1 % of the lattice
@@ -384,25 +385,32 @@ def test_trained_network_gain():
             assert eh[k] <= 0.01 and eh[k] < ep[k], k
 
 
-def test_sweep_trained_network_gain():
-    """The network trained on 2000 trajectories of the batched-sweep generator
-    (weights/surrogate_k100_sweep2000.npz) on two fresh lattices of that
-    generator (uneven sizes, seed 55), 10 blocks of 100 steps from t = 22000
-    (inside its training window): at least twice as fast as the plain FP32
-    lattice update, every field within 3 % of it and at most half as far from
-    it as persistence.  (Measured: 1.3-1.7 % after 10 blocks, persistence
-    4.5-5.6 %; the network trained on 64 fixed 256 x 1024 lattices stays
-    within 1 % on those lattices.)"""
+@pytest.mark.parametrize("lattices", ["256x1024", "uneven"])
+def test_sweep_trained_network_gain(lattices):
+    """The production network, trained on 2000 trajectories of the batched-sweep
+    generator (weights/surrogate_k100_sweep2000.npz), against the plain FP32
+    lattice update on two fresh lattices (seed 55): 256 x 1024 lattices drawn
+    with the sweep's parameters, or the generator's own lattices of uneven
+    size; 10 blocks of 100 steps after 30000 steps of warm-up.  The hybrid is
+    at least twice as fast and needs no fallback; every field stays within 1 %
+    of the lattice update; phi and T are at least 4 times closer to it than
+    persistence, the velocity closer than persistence.  (Measured: 0.51-0.95 %
+    worst field, persistence 3.2-4.0 %.)"""
     import os
     from paper_2306_11320_amd import workloads as wl
-    announce("sweep_trained_network_gain")
+    from paper_2306_11320_amd.train_surrogate import sweep_items
+    announce("sweep_trained_network_gain", lattices)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     net = sur.Surrogate.load(os.path.join(root, "paper_2306_11320_amd", "weights", "surrogate_k100_sweep2000.npz"))
-    res = sur.evaluate(net, wl.sweep(2, seed=55, laplace_p=True), warm=22000, blocks=10, chunk=10, log=None)
+    items = sweep_items(2, 55, 256, 1024) if lattices == "256x1024" else wl.sweep(2, seed=55, laplace_p=True)
+    res = sur.evaluate(net, items, warm=30000, blocks=10, chunk=10, log=None)
     for r in res:
         eh, ep = r["err_hybrid"][-1], r["err_persistence"][-1]
         speedup = sum(r["t_ref_ms"]) / sum(r["t_hybrid_ms"])
         print(f"speedup {speedup:.2f} hybrid {eh} persistence {ep}", flush=True)
         assert speedup >= 2.0
-        assert max(eh.values()) <= 0.03
-        assert max(eh.values()) <= 0.5 * max(ep.values())
+        assert r["fallbacks"] == 0
+        for k in ("phi", "T"):
+            assert eh[k] <= 0.01 and eh[k] <= 0.25 * ep[k], k
+        for k in ("ux", "uy"):
+            assert eh[k] <= 0.01 and eh[k] < ep[k], k
