@@ -31,7 +31,7 @@ extern "C" {
  * in, conv with dilation dil (1 <= dil <= w: taps at (dy, dx) * dil); in has
  * cin in {8, 32} channels; out has 32 channels, FP32 if out_f32 else BF16.
  * bias, res and mask may be NULL (res has out's type; mask is BF16 with 32
- * channels). */
+ * channels).  Frames of n x h x w pixels with n h ceil(w / 32) < 2^30. */
 int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias, const void* d_res,
                 const void* d_mask, void* d_out, int out_f32, int relu_in, int dil, int n, int h, int w,
                 void* stream);

@@ -36,6 +36,8 @@ int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias,
     if (cin != 8 && cin != 32) return bad("sur_conv3x3: cin must be 8 or 32");
     if (n < 1 || h < 1 || w < 1) return bad("sur_conv3x3: need n, h, w >= 1");
     if (dil < 1 || dil > w) return bad("sur_conv3x3: need 1 <= dil <= w");
+    // 32-pixel segments are numbered with 32-bit integers in the kernel
+    if ((long long)n * h * ((w + 31) / 32) >= (1LL << 30)) return bad("sur_conv3x3: more than 2^30 segments");
     if (!aligned16(d_in) || !aligned16(d_w)) return bad("sur_conv3x3: in and w must be 16-byte aligned");
     return check(sur::conv(static_cast<const bf16*>(d_in), cin, static_cast<const bf16*>(d_w), d_bias, d_res,
                            static_cast<const bf16*>(d_mask), d_out, out_f32, relu_in, dil, n, h, w,

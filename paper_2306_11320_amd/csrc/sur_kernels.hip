@@ -75,6 +75,51 @@ __device__ inline void conv_store(const f32x16& acc, float bv, const void* __res
     }
 }
 
+// One 32-pixel segment of a 32-channel layer (row y of frame n, pixels x0 ..
+// x0 + 31).  K block q is tap q / 2, channels 16 (q % 2) + 8 kh ... + 7: the
+// three tap rows (clamped to the frame) and the three tap columns (periodic)
+// are computed once per segment, and all 18 operands are loaded before the
+// first matrix-core op.  A tap row outside the frame contributes nothing: its
+// K blocks take their weight operands from the all-zero block sB[18] (a
+// scalar choice of LDS address per block; the clamped row's activations are
+// finite, so the products are exact zeros, as if the inputs were zeroed by a
+// select per operand register).
+template <bool RELU, bool OUTF32, bool RES, bool MASK>
+__device__ __forceinline__ void conv_seg32(const bf16* __restrict__ in, const bf16x8 (*__restrict__ sB)[64], int lz,
+                                           float bv, const void* __restrict__ res, const bf16* __restrict__ mask,
+                                           void* __restrict__ out, int dil, int H, int W, int n, int y, int x0,
+                                           int m, int kh, int co)
+{
+    constexpr int CIN = 32, NKB = 18;
+    const int xm = x0 + m < W ? x0 + m : W - 1;
+    const bf16* rowp[3];
+    bool rok[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int yy = y + (r - 1) * dil;
+        rok[r] = yy >= 0 && yy < H;
+        rowp[r] = in + ((long long)n * H + (rok[r] ? yy : y)) * W * CIN + 8 * kh;
+    }
+    int xc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int xx = xm + (c - 1) * dil;  // |offset| <= W, so one wrap suffices
+        xc[c] = (xx < 0 ? xx + W : (xx >= W ? xx - W : xx)) * CIN;
+    }
+    bf16x8 a[NKB];
+#pragma unroll
+    for (int q = 0; q < NKB; ++q) {
+        const int tap = q >> 1;
+        a[q] = load8(rowp[tap / 3] + xc[tap % 3] + 16 * (q & 1));
+    }
+    f32x16 acc = {};
+#pragma unroll
+    for (int q = 0; q < NKB; ++q)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[rok[(q >> 1) / 3] ? q : NKB][lz],
+                                                      acc, 0, 0, 0);
+    conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh, co);
+}
+
 // out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + d dy, x + d dx, ci) W[co][tap][ci] )
 // with dilation d; A = relu(in) if RELU.  Epilogue: + bias[co] (if bias);
 // then, if MASK, zero where mask <= 0; then, if RES, + res.  The output is
@@ -82,7 +127,9 @@ __device__ inline void conv_store(const f32x16& acc, float bv, const void* __res
 // are loaded before the first matrix-core op (rows outside the frame load a
 // clamped row and are zeroed), so the loads of a wave are in flight together.
 // A row of W pixels takes ceil(W / 32) segments; in the last one the pixels
-// beyond the row repeat its last pixel and are not stored.
+// beyond the row repeat its last pixel and are not stored.  Segment indices
+// are 32-bit (the host keeps N H ceil(W / 32) below 2^31): 64-bit divisions
+// took ~250 scalar instructions per segment.
 template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
 __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                               const float* __restrict__ bias, const void* __restrict__ res,
@@ -92,17 +139,17 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     constexpr int K = 9 * CIN, NKB = (K + 15) / 16;
     const int lane = threadIdx.x % 64;
     const int segs_per_row = (W + 31) / 32;
-    const long long nseg = (long long)N * H * segs_per_row;
+    const int nseg = N * H * segs_per_row;
     // the segment index is the same for every lane of a wave: kept scalar, so
     // that everything derived from it (row, frame, validity of tap rows) is
     // scalar too
-    const long long wave0 = (long long)blockIdx.x * 4 + (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const long long nwaves = (long long)gridDim.x * 4;
+    const int wave0 = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int nwaves = (int)gridDim.x * 4;
     const int m = lane % 32, kh = lane / 32;
     // the weight operands of the whole K loop are staged once per workgroup
-    // in LDS, in the order the lanes read them
-    __shared__ bf16x8 sB[NKB][64];
-    for (int e = threadIdx.x; e < NKB * 64; e += blockDim.x) {
+    // in LDS, in the order the lanes read them, followed by an all-zero block
+    __shared__ bf16x8 sB[NKB + 1][64];
+    for (int e = threadIdx.x; e < (NKB + 1) * 64; e += blockDim.x) {
         const int q = e / 64, l = e % 64;
         const int kk = q * 16 + 8 * (l / 32);
         bf16x8 v = bf16x8{};
@@ -112,51 +159,18 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     __syncthreads();
     const int co = lane % 32;
     const float bv = bias ? bias[co] : 0.f;
-    for (long long seg = wave0; seg < nseg; seg += nwaves) {
+    for (int seg = wave0; seg < nseg; seg += nwaves) {
         // an index the compiler cannot hoist: the weight operands are read from
         // LDS per segment instead of being held in 72 registers
-        const int lz = lane + 64 * (int)__builtin_amdgcn_readfirstlane((unsigned)(seg >> 40));
-        const int x0 = (int)(seg % segs_per_row) * 32;
-        const long long ny = seg / segs_per_row;
-        const int y = (int)(ny % H), n = (int)(ny / H);
-        const int xm = x0 + m < W ? x0 + m : W - 1;
-        bf16x8 a[NKB];
+        const int lz = lane + 64 * __builtin_amdgcn_readfirstlane((int)((unsigned)seg >> 31));
+        const int x0 = (seg % segs_per_row) * 32;
+        const int ny = seg / segs_per_row;
+        const int y = ny % H, n = ny / H;
         if constexpr (CIN == 32) {
-            // K block q is tap q / 2, channels 16 (q % 2) + 8 kh ... + 7: the
-            // three tap rows (clamped to the frame) and the three tap columns
-            // (periodic) are computed once per segment
-            const bf16* rowp[3];
-            bool rok[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int yy = y + (r - 1) * dil;
-                rok[r] = yy >= 0 && yy < H;
-                rowp[r] = in + ((long long)n * H + (rok[r] ? yy : y)) * W * CIN + 8 * kh;
-            }
-            int xc[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int xx = xm + (c - 1) * dil;  // |offset| <= W, so one wrap suffices
-                xc[c] = (xx < 0 ? xx + W : (xx >= W ? xx - W : xx)) * CIN;
-            }
-#pragma unroll
-            for (int q = 0; q < NKB; ++q) {
-                const int tap = q >> 1;
-                a[q] = load8(rowp[tap / 3] + xc[tap % 3] + 16 * (q & 1));
-            }
-            // a tap row outside the frame contributes nothing: its operands
-            // are zeroed (a select on a scalar condition: zeroing under a
-            // branch held 92 VGPRs against 63)
-#pragma unroll
-            for (int q = 0; q < NKB; ++q)
-                if (!rok[(q >> 1) / 3]) a[q] = bf16x8{};
-            f32x16 acc = {};
-#pragma unroll
-            for (int q = 0; q < NKB; ++q)
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
-            conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh,
-                                          co);
+            conv_seg32<RELU, OUTF32, RES, MASK>(in, sB, lz, bv, res, mask, out, dil, H, W, n, y, x0, m, kh, co);
         } else {
+            const int xm = x0 + m < W ? x0 + m : W - 1;
+            bf16x8 a[NKB];
 #pragma unroll
             for (int q = 0; q < NKB; ++q) {
                 const int kk = q * 16 + 8 * kh;
