@@ -89,6 +89,17 @@ int sur_pack_target(const float* const* d_f0, const float* const* d_f1, int64_t 
 /* Advances the five fields in place by a predicted increment:
  * f_c += delta[:, c] inc[c], c = 0..4 (delta: FP32, 32 channels). */
 int sur_advance(const float* d_delta, int64_t npix, const sur_scales* scales, float* const* d_f, void* stream);
+/* The network's last layer with the state update of sur_advance fused into
+ * its epilogue, on one frame of h x w pixels (h ceil(w / 32) < 2^30):
+ * f_c += (conv(A, w) + bias)_c * inc[c] for c < 5, A = max(in, 0) if relu_in,
+ * in BF16 NHWC with 32 channels, w and bias as for sur_conv3x3 with cin = 32,
+ * dilation dil.  Bitwise equal to sur_conv3x3 into an FP32 buffer followed by
+ * sur_advance, without that buffer (the 32 FP32 channels of the increment are
+ * neither written nor read).  d_f: five FP32 device fields of h*w (phi, ux,
+ * uy, T, p), updated in place.  Errors: NULL pointers, h or w < 1, dil out of
+ * [1, w], too many segments or misaligned in / w. */
+int sur_conv3x3_advance(const void* d_in, const void* d_w, const float* d_bias, int relu_in, int dil, int h, int w,
+                        const sur_scales* scales, float* const* d_f, void* stream);
 /* Light-phase volume sum (1 - phi)/2 of a frame, in FP64, into *d_out (device),
  * through `groups` partials in d_part (8*groups doubles), summed in a fixed order. */
 int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int groups, double* d_out, void* stream);

@@ -144,6 +144,21 @@ int sur_advance(const float* d_delta, int64_t npix, const sur_scales* scales, fl
     return check(sur::advance(d_delta, npix, sc, f, static_cast<hipStream_t>(stream)), "sur_advance");
 }
 
+int sur_conv3x3_advance(const void* d_in, const void* d_w, const float* d_bias, int relu_in, int dil, int h, int w,
+                        const sur_scales* scales, float* const* d_f, void* stream)
+{
+    sur::State5 f;
+    sur::Scales sc;
+    if (!d_in || !d_w || !get_state(d_f, f) || !get_scales(scales, sc)) return bad("sur_conv3x3_advance: bad arguments");
+    if (h < 1 || w < 1) return bad("sur_conv3x3_advance: need h, w >= 1");
+    if (dil < 1 || dil > w) return bad("sur_conv3x3_advance: need 1 <= dil <= w");
+    if ((long long)h * ((w + 31) / 32) >= (1LL << 30)) return bad("sur_conv3x3_advance: more than 2^30 segments");
+    if (!aligned16(d_in) || !aligned16(d_w)) return bad("sur_conv3x3_advance: in and w must be 16-byte aligned");
+    return check(sur::conv_advance(static_cast<const bf16*>(d_in), static_cast<const bf16*>(d_w), d_bias, relu_in, dil,
+                                   h, w, sc, f, static_cast<hipStream_t>(stream)),
+                 "sur_conv3x3_advance");
+}
+
 int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int groups, double* d_out, void* stream)
 {
     if (!d_phi || !d_part || !d_out || h < 1 || w < 1 || groups < 1) return bad("sur_light_volume: bad arguments");

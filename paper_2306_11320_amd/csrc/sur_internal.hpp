@@ -32,6 +32,8 @@ hipError_t mse(const float* delta, const float* target, long long npix, int nout
 hipError_t pack(const State5& f, long long npix, int w, const Scales& sc, bf16* x, hipStream_t s);
 hipError_t pack_target(const State5& f0, const State5& f1, long long npix, const Scales& sc, float* t, hipStream_t s);
 hipError_t advance(const float* delta, long long npix, const Scales& sc, const State5& f, hipStream_t s);
+hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
+                        const Scales& sc, const State5& f, hipStream_t s);
 hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,
                       int groups, double* out, hipStream_t s);
 

@@ -84,11 +84,9 @@ __device__ inline void conv_store(const f32x16& acc, float bv, const void* __res
 // scalar choice of LDS address per block; the clamped row's activations are
 // finite, so the products are exact zeros, as if the inputs were zeroed by a
 // select per operand register).
-template <bool RELU, bool OUTF32, bool RES, bool MASK>
-__device__ __forceinline__ void conv_seg32(const bf16* __restrict__ in, const bf16x8 (*__restrict__ sB)[64], int lz,
-                                           float bv, const void* __restrict__ res, const bf16* __restrict__ mask,
-                                           void* __restrict__ out, int dil, int H, int W, int n, int y, int x0,
-                                           int m, int kh, int co)
+template <bool RELU>
+__device__ __forceinline__ f32x16 conv_seg32(const bf16* __restrict__ in, const bf16x8 (*__restrict__ sB)[64], int lz,
+                                             int dil, int H, int W, int n, int y, int x0, int m, int kh)
 {
     constexpr int CIN = 32, NKB = 18;
     const int xm = x0 + m < W ? x0 + m : W - 1;
@@ -117,7 +115,23 @@ __device__ __forceinline__ void conv_seg32(const bf16* __restrict__ in, const bf
     for (int q = 0; q < NKB; ++q)
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[rok[(q >> 1) / 3] ? q : NKB][lz],
                                                       acc, 0, 0, 0);
-    conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh, co);
+    return acc;
+}
+
+// Stages the weight operands of a 32-channel layer in LDS, in the order the
+// lanes read them, followed by an all-zero block (every work-item calls it).
+template <int CIN>
+__device__ inline void stage_weights(const bf16* __restrict__ w, bf16x8 (*sB)[64])
+{
+    constexpr int K = 9 * CIN, NKB = (K + 15) / 16;
+    for (int e = threadIdx.x; e < (NKB + 1) * 64; e += blockDim.x) {
+        const int q = e / 64, l = e % 64;
+        const int kk = q * 16 + 8 * (l / 32);
+        bf16x8 v = bf16x8{};
+        if (kk < K) v = load8(w + ((long long)(l % 32) * 9 + kk / CIN) * CIN + kk % CIN);  // column co = l % 32
+        sB[q][l] = v;
+    }
+    __syncthreads();
 }
 
 // out[n][y][x][co] = epilogue( sum_{tap, ci} A(n, y + d dy, x + d dx, ci) W[co][tap][ci] )
@@ -147,16 +161,8 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     const int nwaves = (int)gridDim.x * 4;
     const int m = lane % 32, kh = lane / 32;
     // the weight operands of the whole K loop are staged once per workgroup
-    // in LDS, in the order the lanes read them, followed by an all-zero block
     __shared__ bf16x8 sB[NKB + 1][64];
-    for (int e = threadIdx.x; e < (NKB + 1) * 64; e += blockDim.x) {
-        const int q = e / 64, l = e % 64;
-        const int kk = q * 16 + 8 * (l / 32);
-        bf16x8 v = bf16x8{};
-        if (kk < K) v = load8(w + ((long long)(l % 32) * 9 + kk / CIN) * CIN + kk % CIN);  // column co = l % 32
-        sB[q][l] = v;
-    }
-    __syncthreads();
+    stage_weights<CIN>(w, sB);
     const int co = lane % 32;
     const float bv = bias ? bias[co] : 0.f;
     for (int seg = wave0; seg < nseg; seg += nwaves) {
@@ -167,7 +173,9 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
         const int ny = seg / segs_per_row;
         const int y = ny % H, n = ny / H;
         if constexpr (CIN == 32) {
-            conv_seg32<RELU, OUTF32, RES, MASK>(in, sB, lz, bv, res, mask, out, dil, H, W, n, y, x0, m, kh, co);
+            const f32x16 acc = conv_seg32<RELU>(in, sB, lz, dil, H, W, n, y, x0, m, kh);
+            conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh,
+                                          co);
         } else {
             const int xm = x0 + m < W ? x0 + m : W - 1;
             bf16x8 a[NKB];
@@ -191,6 +199,50 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(RELU ? relu8(a[q]) : a[q], sB[q][lz], acc, 0, 0, 0);
             conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W, kh,
                                           co);
+        }
+    }
+}
+
+// The network's last layer with the state update fused into its epilogue,
+// on one frame: f_c += (conv(A, w) + bias)_c inc[c] for the five state fields
+// c < 5 (A = relu(in) if RELU; 32 input channels).  Equal to k_conv with an
+// FP32 output followed by k_advance (the same sums, the same roundings), but
+// the 32 FP32 channels of the increment are never written or read back.
+template <bool RELU>
+__global__ __launch_bounds__(256) void k_conv_advance(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                                      const float* __restrict__ bias, State5 f, Scales sc, int dil,
+                                                      int H, int W)
+{
+    constexpr int NKB = 18;
+    const int lane = threadIdx.x % 64;
+    const int segs_per_row = (W + 31) / 32;
+    const int nseg = H * segs_per_row;
+    const int wave0 = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int nwaves = (int)gridDim.x * 4;
+    const int m = lane % 32, kh = lane / 32, co = lane % 32;
+    __shared__ bf16x8 sB[NKB + 1][64];
+    stage_weights<32>(w, sB);
+    const float bv = bias ? bias[co] : 0.f;
+    // lanes of channels 0..4 update their field; the others only feed the
+    // matrix cores
+    const bool upd = co < 5;
+    float* fv = const_cast<float*>(f.v[upd ? co : 0]);
+    const float ic = sc.inc[upd ? co : 0];
+    for (int seg = wave0; seg < nseg; seg += nwaves) {
+        const int lz = lane + 64 * __builtin_amdgcn_readfirstlane((int)((unsigned)seg >> 31));
+        const int x0 = (seg % segs_per_row) * 32;
+        const int y = seg / segs_per_row;
+        const f32x16 acc = conv_seg32<RELU>(in, sB, lz, dil, H, W, 0, y, x0, m, kh);
+        if (upd) {
+            const long long p0 = (long long)y * W + x0 + 4 * kh;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int dx = 8 * (i / 4) + (i % 4);
+                if (x0 + 4 * kh + dx < W) {
+                    const float v = acc[i] + bv;
+                    fv[p0 + dx] = fv[p0 + dx] + v * ic;
+                }
+            }
         }
     }
 }
@@ -491,6 +543,20 @@ hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const
 {
     if (cin == 8) conv_c<8>(in, w, bias, res, mask, out, out_f32, relu_in, dil, N, H, W, s);
     else conv_c<32>(in, w, bias, res, mask, out, out_f32, relu_in, dil, N, H, W, s);
+    return hipGetLastError();
+}
+
+hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
+                        const Scales& sc, const State5& f, hipStream_t s)
+{
+    const long long segs = (long long)H * ((W + 31) / 32);
+    long long groups = (segs + 3) / 4;
+    if (groups > 1536) groups = 1536;
+    if (relu_in)
+        hipLaunchKernelGGL(k_conv_advance<true>, dim3((unsigned)groups), dim3(256), 0, s, in, w, bias, f, sc, dil, H, W);
+    else
+        hipLaunchKernelGGL(k_conv_advance<false>, dim3((unsigned)groups), dim3(256), 0, s, in, w, bias, f, sc, dil, H,
+                           W);
     return hipGetLastError();
 }
 

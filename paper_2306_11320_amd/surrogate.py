@@ -74,6 +74,7 @@ def lib():
         L.sur_pack.argtypes = [pp, ip, ip, sp, vp, vp]
         L.sur_pack_target.argtypes = [pp, pp, i64, sp, vp, vp]
         L.sur_advance.argtypes = [vp, i64, sp, pp, vp]
+        L.sur_conv3x3_advance.argtypes = [vp, vp, vp, ip, ip, ip, ip, sp, pp, vp]
         L.sur_light_volume.argtypes = [vp, ip, ip, vp, ip, vp, vp]
         L.sur_judge.argtypes = [pp, pp, ip, ip, sp, vp, ip, vp, vp]
         L.sur_judge_noscratch.argtypes = [pp, pp, ip, ip, sp, ip, vp, vp]
@@ -143,6 +144,12 @@ def sur_pack_target(f0, f1, sc: SurScales, t, stream):
 
 def sur_advance(delta, sc: SurScales, f, stream):
     _ck(lib().sur_advance(_p(delta), f["phi"].numel(), C.byref(sc), _state(f), _s(stream)))
+
+
+def sur_conv3x3_advance(x, w, bias, relu_in, sc: SurScales, f, stream, dil=1):
+    h, wd = f["phi"].shape
+    _ck(lib().sur_conv3x3_advance(_p(x), _p(w), _p(bias), int(relu_in), int(dil), h, wd, C.byref(sc), _state(f),
+                                  _s(stream)))
 
 
 def sur_light_volume(phi, part, out, stream):
@@ -231,12 +238,11 @@ class Surrogate:
         return t
 
     # ---- network ----
-    def forward(self, x, keep: bool = False):
-        """x: BF16 [N, H, W, 8].  Returns delta (FP32 [N, H, W, 32]) and, if
-        keep, the BF16 activations h0..h4 for the backward pass."""
-        torch = self.torch
+    def _hidden(self, x, keep: bool):
+        """Layers 0..4 on x (BF16 [N, H, W, 8]): the last hidden activation and,
+        if keep, all five."""
         N, H, W, _ = x.shape
-        bf = torch.bfloat16
+        bf = self.torch.bfloat16
         hs = []
         h = self._get("h0", (N, H, W, 32), bf)
         d = self.dil
@@ -247,8 +253,15 @@ class Surrogate:
             sur_conv3x3(h, 32, self.Wb[r], self.b[r], h, None, hn, True, self.stream, d[r])
             h = hn
             hs.append(h)
-        delta = self._get("delta", (N, H, W, 32), torch.float32)
-        sur_conv3x3(h, 32, self.Wb[5], self.b[5], None, None, delta, True, self.stream, d[5])
+        return h, hs
+
+    def forward(self, x, keep: bool = False):
+        """x: BF16 [N, H, W, 8].  Returns delta (FP32 [N, H, W, 32]) and, if
+        keep, the BF16 activations h0..h4 for the backward pass."""
+        N, H, W, _ = x.shape
+        h, hs = self._hidden(x, keep)
+        delta = self._get("delta", (N, H, W, 32), self.torch.float32)
+        sur_conv3x3(h, 32, self.Wb[5], self.b[5], None, None, delta, True, self.stream, self.dil[5])
         return delta, (hs if keep else None)
 
     def _backward(self, x, hs, gd, gW, gb, wpart, bpart, groups):
@@ -349,8 +362,9 @@ class Surrogate:
         ny, nx = state["phi"].shape
         x = self._get("x1", (1, ny, nx, 8), self.torch.bfloat16)
         sur_pack(state, sc, x, self.stream)
-        delta, _ = self.forward(x)
-        sur_advance(delta, sc, state, self.stream)
+        h, _ = self._hidden(x, False)
+        # the output layer adds its increment to the state directly
+        sur_conv3x3_advance(h, self.Wb[5], self.b[5], True, sc, state, self.stream, self.dil[5])
 
 
 # ---- data from the lattice Boltzmann update --------------------------------

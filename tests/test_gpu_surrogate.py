@@ -297,6 +297,41 @@ def test_pack_target_and_advance(stream):
         assert torch.allclose(g[k], f1[k], rtol=1e-5, atol=1e-5), k
 
 
+@pytest.mark.parametrize("relu_in", [False, True])
+@pytest.mark.parametrize("dil,W", [(1, 64), (16, 256), (3, 200), (2, 45), (1, 7)])
+def test_conv_advance_fused(relu_in, dil, W, stream):
+    """The output layer with the state update fused (sur_conv3x3_advance) is
+    bitwise equal to the convolution into an FP32 buffer followed by
+    sur_advance, on frames with whole and ragged last segments; and that
+    update matches the FP64 reference convolution."""
+    announce("conv_advance_fused", relu_in, dil, W)
+    rng = np.random.default_rng(7 + relu_in + 10 * dil + W)
+    H = 37
+    cfg = _cfg_scales()
+    sc = sur.scales_of(cfg, (0.01, 0.02, 0.03, 0.04, 0.05))
+    x = cr.bf16_round(rng.standard_normal((1, H, W, 32)))
+    w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, 32)))
+    b = rng.standard_normal(32).astype(np.float32)
+    f0 = _rand_state(rng, H, W)
+    xd, wd, bd = dev(stream, t_bf16(x), t_bf16(w), t_f32(b))
+    g1 = {k: v.clone() for k, v in f0.items()}
+    g2 = {k: v.clone() for k, v in f0.items()}
+    delta = torch.empty((1, H, W, 32), device="cuda")
+    dev(stream, delta, *g1.values(), *g2.values())
+    sur.sur_conv3x3(xd, 32, wd, bd, None, None, delta, relu_in, stream, dil)
+    sur.sur_advance(delta, sc, g1, stream)
+    sur.sur_conv3x3_advance(xd, wd, bd, relu_in, sc, g2, stream, dil)
+    stream.synchronize()
+    for k in sur.FIELDS:
+        assert torch.equal(g1[k], g2[k]), k
+    a = cr.relu(x) if relu_in else x
+    ref = cr.conv(a, w, b, dil)[0]
+    for c, k in enumerate(sur.FIELDS):
+        want = f0[k].double().cpu().numpy() + ref[..., c] * sc.inc[c]
+        got = g2[k].double().cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-5 * (np.abs(want).max() + 1.0), k
+
+
 def test_light_volume_and_judge(stream):
     announce("volume_judge")
     rng = np.random.default_rng(22)
