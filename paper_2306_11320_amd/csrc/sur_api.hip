@@ -38,7 +38,8 @@ int sur_conv3x3(const void* d_in, int cin, const void* d_w, const float* d_bias,
     if (dil < 1 || dil > w) return bad("sur_conv3x3: need 1 <= dil <= w");
     // 32-pixel segments are numbered with 32-bit integers in the kernel
     if ((long long)n * h * ((w + 31) / 32) >= (1LL << 30)) return bad("sur_conv3x3: more than 2^30 segments");
-    if (!aligned16(d_in) || !aligned16(d_w)) return bad("sur_conv3x3: in and w must be 16-byte aligned");
+    if (!aligned16(d_in) || !aligned16(d_w) || !aligned16(d_out) || (d_res && !aligned16(d_res)))
+        return bad("sur_conv3x3: in, w, res and out must be 16-byte aligned");
     return check(sur::conv(static_cast<const bf16*>(d_in), cin, static_cast<const bf16*>(d_w), d_bias, d_res,
                            static_cast<const bf16*>(d_mask), d_out, out_f32, relu_in, dil, n, h, w,
                            static_cast<hipStream_t>(stream)),

@@ -75,6 +75,35 @@ __device__ inline void conv_store(const f32x16& acc, float bv, const void* __res
     }
 }
 
+// Per-wave LDS tile of the output layer's transposed epilogue: half a segment
+// (16 pixels) of the accumulator, 32 channels in FP32, rows of kTP floats (the
+// two halves of a wave's write, 4 rows apart, fall on disjoint banks).  The
+// same transposition for the hidden layers' BF16 stores and residual loads
+// (16-byte accesses, 4 memory instructions per segment instead of 32) was
+// measured without gain: their cost is the bytes moved, not the instructions.
+constexpr int kTP = 40;
+typedef float TTile[16][kTP];
+
+// Orders a wave's LDS writes before its lanes read what other lanes wrote.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Writes half h (pixels 16 h .. 16 h + 15 of the segment) of acc + bias to
+// the tile: element i of the accumulator is pixel 8 (i / 4) + 4 kh + i % 4,
+// channel co.
+__device__ inline void tile_half(TTile& T, const f32x16& acc, float bv, int h, int kh, int co)
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = 8 * h + j;
+        T[8 * (i / 4) + 4 * kh + i % 4 - 16 * h][co] = acc[i] + bv;
+    }
+}
+
 // One 32-pixel segment of a 32-channel layer (row y of frame n, pixels x0 ..
 // x0 + 31).  K block q is tap q / 2, channels 16 (q % 2) + 8 kh ... + 7: the
 // three tap rows (clamped to the frame) and the three tap columns (periodic)
@@ -221,27 +250,34 @@ __global__ __launch_bounds__(256) void k_conv_advance(const bf16* __restrict__ i
     const int nwaves = (int)gridDim.x * 4;
     const int m = lane % 32, kh = lane / 32, co = lane % 32;
     __shared__ bf16x8 sB[NKB + 1][64];
+    __shared__ TTile sT[4];
     stage_weights<32>(w, sB);
+    TTile& T = sT[threadIdx.x / 64];
     const float bv = bias ? bias[co] : 0.f;
-    // lanes of channels 0..4 update their field; the others only feed the
-    // matrix cores
-    const bool upd = co < 5;
-    float* fv = const_cast<float*>(f.v[upd ? co : 0]);
-    const float ic = sc.inc[upd ? co : 0];
     for (int seg = wave0; seg < nseg; seg += nwaves) {
         const int lz = lane + 64 * __builtin_amdgcn_readfirstlane((int)((unsigned)seg >> 31));
         const int x0 = (seg % segs_per_row) * 32;
         const int y = seg / segs_per_row;
         const f32x16 acc = conv_seg32<RELU>(in, sB, lz, dil, H, W, 0, y, x0, m, kh);
-        if (upd) {
-            const long long p0 = (long long)y * W + x0 + 4 * kh;
+        // through the transposition tile, lane l < 32 takes pixel x0 + l of the
+        // five state channels: five coalesced 128-byte rows per segment
+        float v[5];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int dx = 8 * (i / 4) + (i % 4);
-                if (x0 + 4 * kh + dx < W) {
-                    const float v = acc[i] + bv;
-                    fv[p0 + dx] = fv[p0 + dx] + v * ic;
-                }
+        for (int h = 0; h < 2; ++h) {
+            tile_half(T, acc, bv, h, kh, co);
+            wave_sync();
+            if (lane / 16 == h) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) v[c] = T[lane % 16][c];
+            }
+            wave_sync();
+        }
+        if (lane < 32 && x0 + lane < W) {
+            const long long p = (long long)y * W + x0 + lane;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                float* fc = const_cast<float*>(f.v[c]);
+                fc[p] = fc[p] + v[c] * sc.inc[c];
             }
         }
     }
