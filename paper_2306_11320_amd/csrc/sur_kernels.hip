@@ -232,6 +232,120 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     }
 }
 
+// A 32-channel layer with dilation d <= 16 by columns: a workgroup of four
+// waves computes the output rows y0, y0 + d, y0 + 2d, y0 + 3d of one 32-pixel
+// column (wave k: row y0 + k d).  The six input rows they read (y0 - d ...
+// y0 + 4d; rows outside the frame clamped into it, their taps then take the
+// zero weight block) are staged once in LDS over the column's window of
+// 32 + 2d pixels (periodic in x), with the ReLU applied as they are staged,
+// and the 18 operands of each segment are read from there: each input pixel
+// is loaded ~1.5 times per segment instead of 9 times.  Pixels are padded to
+// 80 bytes, so a wave's operand reads meet distinct banks.  The products and
+// their order are those of k_conv.
+constexpr int kColRows = 6, kColPix = 64, kColPS = 40;
+
+// ADV: the output layer of inference, whose epilogue adds the increment to the
+// five state fields f (as k_conv_advance; N = 1).
+template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false>
+__global__ __launch_bounds__(256) void k_conv_col(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                                  const float* __restrict__ bias, const void* __restrict__ res,
+                                                  const bf16* __restrict__ mask, void* __restrict__ out, int dil, int N,
+                                                  int H, int W, State5 f, Scales sc)
+{
+    constexpr int NKB = 18;
+    const int lane = threadIdx.x % 64;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int m = lane % 32, kh = lane / 32, co = lane % 32;
+    __shared__ bf16x8 sB[NKB + 1][64];
+    __shared__ __attribute__((aligned(16))) bf16 sX[kColRows][kColPix][kColPS];
+    // ADV: per-wave transposition tile of the five state channels (16 pixels)
+    __shared__ float sT[ADV ? 4 : 1][16][8];
+    stage_weights<32>(w, sB);
+    const float bv = bias ? bias[co] : 0.f;
+    const int SC = (W + 31) / 32;
+    const int G = ((H + dil - 1) / dil + 3) / 4;  // groups of four rows per residue class of y mod d
+    const int nitems = N * dil * G * SC;
+    const int win = 32 + 2 * dil;
+    for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
+        const int sx = t % SC;
+        const int u = t / SC;
+        const int g = u % G, r = (u / G) % dil, n = u / G / dil;
+        const int y0 = r + 4 * g * dil;
+        if (y0 >= H) continue;  // the same for the whole workgroup
+        const int x0 = sx * 32;
+        __syncthreads();  // every wave is done with the previous item's rows
+        // one row per pass: work-item (i, c) = (tid / 4, tid % 4) takes channels
+        // 8c .. 8c + 7 of window pixel i (win <= 64 pixels, 4 chunks each)
+        // (work-items beyond the window load its last pixel and store nothing)
+        const int c = threadIdx.x % 4, i = threadIdx.x / 4;
+        int xx = x0 - dil + (i < win ? i : win - 1);
+        if (xx < 0 || xx >= W) xx = ((xx % W) + W) % W;
+        const int off = xx * 32 + 8 * c;
+        bf16x8 v[kColRows];
+#pragma unroll
+        for (int j = 0; j < kColRows; ++j) {
+            int yy = y0 + (j - 1) * dil;
+            yy = yy < 0 ? 0 : (yy >= H ? H - 1 : yy);
+            const bf16* rowp = in + ((long long)n * H + yy) * W * 32;  // the same for the whole workgroup
+            v[j] = load8(rowp + off);
+        }
+        if (i < win) {
+#pragma unroll
+            for (int j = 0; j < kColRows; ++j)
+                *reinterpret_cast<bf16x8*>(&sX[j][i][8 * c]) = RELU ? relu8(v[j]) : v[j];
+        }
+        __syncthreads();
+        const int y = y0 + wave * dil;
+        if (y < H) {
+            bool rok[3];
+#pragma unroll
+            for (int q3 = 0; q3 < 3; ++q3) {
+                const int yy = y + (q3 - 1) * dil;
+                rok[q3] = yy >= 0 && yy < H;
+            }
+            f32x16 acc = {};
+#pragma unroll
+            for (int q = 0; q < NKB; ++q) {
+                const int tap = q >> 1, tr = tap / 3, tc = tap % 3;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sX[wave + tr][m + tc * dil][16 * (q & 1) + 8 * kh]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, sB[rok[tr] ? q : NKB][lane], acc, 0, 0, 0);
+            }
+            if constexpr (ADV) {
+                // lane l < 32 takes pixel x0 + l of the five state channels
+                float (*T)[8] = sT[wave];
+                float v[5];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (co < 5) {
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const int ii = 8 * h + jj;
+                            T[8 * (ii / 4) + 4 * kh + ii % 4 - 16 * h][co] = acc[ii] + bv;
+                        }
+                    }
+                    wave_sync();
+                    if (lane / 16 == h) {
+#pragma unroll
+                        for (int cc = 0; cc < 5; ++cc) v[cc] = T[lane % 16][cc];
+                    }
+                    wave_sync();
+                }
+                if (lane < 32 && x0 + lane < W) {
+                    const long long p = (long long)y * W + x0 + lane;
+#pragma unroll
+                    for (int cc = 0; cc < 5; ++cc) {
+                        float* fc = const_cast<float*>(f.v[cc]);
+                        fc[p] = fc[p] + v[cc] * sc.inc[cc];
+                    }
+                }
+            } else {
+                conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W,
+                                              kh, co);
+            }
+        }
+    }
+}
+
 // The network's last layer with the state update fused into its epilogue,
 // on one frame: f_c += (conv(A, w) + bias)_c inc[c] for the five state fields
 // c < 5 (A = relu(in) if RELU; 32 input channels).  Equal to k_conv with an
@@ -541,10 +655,25 @@ __global__ __launch_bounds__(256) void k_frame_final(const double* __restrict__ 
 
 // ---- launchers ----
 
+// Workgroups of a column-kernel launch: every column's group of four rows of
+// one residue class of y mod dil is one work item.
+static unsigned col_groups(int dil, int N, int H, int W)
+{
+    const long long items = (long long)N * dil * (((H + dil - 1) / dil + 3) / 4) * ((W + 31) / 32);
+    return (unsigned)(items < 768 ? items : 768);
+}
+
 template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
 static void conv_t(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
                    int dil, int N, int H, int W, hipStream_t s)
 {
+    if (CIN == 32 && dil <= 16) {
+        // by columns: a resident grid (three workgroups per CU) walks the
+        // columns' groups of four rows
+        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W)), dim3(256), 0, s, in,
+                           w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
+        return;
+    }
     // a resident grid (6 waves per SIMD on 256 CUs) walks the segments, so
     // each workgroup stages the weights once
     const long long segs = (long long)N * H * ((W + 31) / 32);
@@ -585,6 +714,15 @@ hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const
 hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
                         const Scales& sc, const State5& f, hipStream_t s)
 {
+    if (dil <= 16) {
+        if (relu_in)
+            hipLaunchKernelGGL((k_conv_col<true, false, false, false, true>), dim3(col_groups(dil, 1, H, W)), dim3(256),
+                               0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+        else
+            hipLaunchKernelGGL((k_conv_col<false, false, false, false, true>), dim3(col_groups(dil, 1, H, W)),
+                               dim3(256), 0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+        return hipGetLastError();
+    }
     const long long segs = (long long)H * ((W + 31) / 32);
     long long groups = (segs + 3) / 4;
     if (groups > 1536) groups = 1536;

@@ -58,11 +58,12 @@ def stream():
 @pytest.mark.parametrize("cin", [8, 32])
 @pytest.mark.parametrize("relu_in", [False, True])
 @pytest.mark.parametrize("dil,W", [(1, 64), (3, 64), (1, 256), (3, 256), (16, 256), (2, 128),
-                                   (1, 129), (3, 200), (16, 41), (1, 7)])
+                                   (1, 129), (3, 200), (16, 41), (1, 7), (20, 64), (17, 45)])
 def test_conv_forward(cin, relu_in, dil, W, stream):
     """Frame widths of one to eight 32-pixel segments per row (periodic wrap at
     both ends of the row), ragged widths whose last segment is partly outside
-    the row, and dilations up to 16."""
+    the row, and dilations up to 16 (32 input channels: the kernel by columns
+    with staged input rows) and beyond (the kernel by segments)."""
     rng = np.random.default_rng(cin + relu_in + 10 * dil + W)
     N, H = 2, 5
     announce("conv_forward", cin, relu_in, dil, W)
@@ -298,7 +299,7 @@ def test_pack_target_and_advance(stream):
 
 
 @pytest.mark.parametrize("relu_in", [False, True])
-@pytest.mark.parametrize("dil,W", [(1, 64), (16, 256), (3, 200), (2, 45), (1, 7)])
+@pytest.mark.parametrize("dil,W", [(1, 64), (16, 256), (3, 200), (2, 45), (1, 7), (20, 64)])
 def test_conv_advance_fused(relu_in, dil, W, stream):
     """The output layer with the state update fused (sur_conv3x3_advance) is
     bitwise equal to the convolution into an FP32 buffer followed by
