@@ -232,67 +232,77 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
     }
 }
 
-// A 32-channel layer with dilation d <= 16 by columns: a workgroup of four
-// waves computes the output rows y0, y0 + d, y0 + 2d, y0 + 3d of one 32-pixel
-// column (wave k: row y0 + k d).  The six input rows they read (y0 - d ...
-// y0 + 4d; rows outside the frame clamped into it, their taps then take the
-// zero weight block) are staged once in LDS over the column's window of
-// 32 + 2d pixels (periodic in x), with the ReLU applied as they are staged,
-// and the 18 operands of each segment are read from there: each input pixel
-// is loaded ~1.5 times per segment instead of 9 times.  Pixels are padded to
+// A 32-channel layer with dilation d <= 16 by columns: a workgroup of kColRW
+// waves computes the output rows y0, y0 + d, ..., y0 + (kColRW - 1) d of one
+// 32-pixel column (wave k: row y0 + k d).  The kColRW + 2 input rows they read
+// (y0 - d ... y0 + kColRW d; rows outside the frame clamped into it, their
+// taps then take the zero weight block) are staged once in LDS over the
+// column's window of 32 + 2d pixels (periodic in x), with the ReLU applied as
+// they are staged, and the 18 operands of each segment are read from there:
+// each input pixel is loaded ~1.25 times per segment instead of 9 times.  Pixels are padded to
 // 80 bytes, so a wave's operand reads meet distinct banks.  The products and
 // their order are those of k_conv.
-constexpr int kColRows = 6, kColPix = 64, kColPS = 40;
+constexpr int kColPix = 64, kColPS = 40;
+// Output rows (waves) per workgroup: eight (ten staged rows, 70 KB of LDS, two
+// workgroups and 4 waves per SIMD) measured 12-14% faster per network block
+// than four (six staged rows, 50 KB, three workgroups, 3 waves per SIMD).
+constexpr int kColRW = 8;
+constexpr int kColRows = kColRW + 2;
 
 // ADV: the output layer of inference, whose epilogue adds the increment to the
 // five state fields f (as k_conv_advance; N = 1).
 template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false>
-__global__ __launch_bounds__(256) void k_conv_col(const bf16* __restrict__ in, const bf16* __restrict__ w,
-                                                  const float* __restrict__ bias, const void* __restrict__ res,
-                                                  const bf16* __restrict__ mask, void* __restrict__ out, int dil, int N,
-                                                  int H, int W, State5 f, Scales sc)
+__global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                                          const float* __restrict__ bias, const void* __restrict__ res,
+                                                          const bf16* __restrict__ mask, void* __restrict__ out,
+                                                          int dil, int N, int H, int W, State5 f, Scales sc)
 {
-    constexpr int NKB = 18;
+    constexpr int NKB = 18, RW = kColRW;
     const int lane = threadIdx.x % 64;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int m = lane % 32, kh = lane / 32, co = lane % 32;
     __shared__ bf16x8 sB[NKB + 1][64];
     __shared__ __attribute__((aligned(16))) bf16 sX[kColRows][kColPix][kColPS];
     // ADV: per-wave transposition tile of the five state channels (16 pixels)
-    __shared__ float sT[ADV ? 4 : 1][16][8];
+    __shared__ float sT[ADV ? RW : 1][16][8];
     stage_weights<32>(w, sB);
     const float bv = bias ? bias[co] : 0.f;
     const int SC = (W + 31) / 32;
-    const int G = ((H + dil - 1) / dil + 3) / 4;  // groups of four rows per residue class of y mod d
+    const int G = ((H + dil - 1) / dil + RW - 1) / RW;  // groups of RW rows per residue class of y mod d
     const int nitems = N * dil * G * SC;
     const int win = 32 + 2 * dil;
     for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
         const int sx = t % SC;
         const int u = t / SC;
         const int g = u % G, r = (u / G) % dil, n = u / G / dil;
-        const int y0 = r + 4 * g * dil;
+        const int y0 = r + RW * g * dil;
         if (y0 >= H) continue;  // the same for the whole workgroup
         const int x0 = sx * 32;
         __syncthreads();  // every wave is done with the previous item's rows
         // one row per pass: work-item (i, c) = (tid / 4, tid % 4) takes channels
         // 8c .. 8c + 7 of window pixel i (win <= 64 pixels, 4 chunks each)
         // (work-items beyond the window load its last pixel and store nothing)
-        const int c = threadIdx.x % 4, i = threadIdx.x / 4;
+        // (RW / 4 rows per pass: work-item t takes row t / 256 of the pass)
+        constexpr int RP = RW / 4, NPASS = (kColRows + RP - 1) / RP;
+        const int c = threadIdx.x % 4, i = (threadIdx.x % 256) / 4, jr = threadIdx.x / 256;
         int xx = x0 - dil + (i < win ? i : win - 1);
         if (xx < 0 || xx >= W) xx = ((xx % W) + W) % W;
         const int off = xx * 32 + 8 * c;
-        bf16x8 v[kColRows];
+        bf16x8 v[NPASS];
 #pragma unroll
-        for (int j = 0; j < kColRows; ++j) {
+        for (int k = 0; k < NPASS; ++k) {
+            const int j = k * RP + jr;
             int yy = y0 + (j - 1) * dil;
             yy = yy < 0 ? 0 : (yy >= H ? H - 1 : yy);
-            const bf16* rowp = in + ((long long)n * H + yy) * W * 32;  // the same for the whole workgroup
-            v[j] = load8(rowp + off);
+            const bf16* rowp = in + ((long long)n * H + yy) * W * 32;
+            if (j < kColRows) v[k] = load8(rowp + off);
         }
         if (i < win) {
 #pragma unroll
-            for (int j = 0; j < kColRows; ++j)
-                *reinterpret_cast<bf16x8*>(&sX[j][i][8 * c]) = RELU ? relu8(v[j]) : v[j];
+            for (int k = 0; k < NPASS; ++k) {
+                const int j = k * RP + jr;
+                if (j < kColRows) *reinterpret_cast<bf16x8*>(&sX[j][i][8 * c]) = RELU ? relu8(v[k]) : v[k];
+            }
         }
         __syncthreads();
         const int y = y0 + wave * dil;
@@ -659,8 +669,9 @@ __global__ __launch_bounds__(256) void k_frame_final(const double* __restrict__ 
 // one residue class of y mod dil is one work item.
 static unsigned col_groups(int dil, int N, int H, int W)
 {
-    const long long items = (long long)N * dil * (((H + dil - 1) / dil + 3) / 4) * ((W + 31) / 32);
-    return (unsigned)(items < 768 ? items : 768);
+    const long long items = (long long)N * dil * (((H + dil - 1) / dil + kColRW - 1) / kColRW) * ((W + 31) / 32);
+    const long long cap = 256 * (kColRW == 4 ? 3 : 2);  // resident workgroups (bound by LDS)
+    return (unsigned)(items < cap ? items : cap);
 }
 
 template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
@@ -670,7 +681,7 @@ static void conv_t(const bf16* in, const bf16* w, const float* bias, const void*
     if (CIN == 32 && dil <= 16) {
         // by columns: a resident grid (three workgroups per CU) walks the
         // columns' groups of four rows
-        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W)), dim3(256), 0, s, in,
+        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W)), dim3(64 * kColRW), 0, s, in,
                            w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
         return;
     }
@@ -716,11 +727,11 @@ hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int re
 {
     if (dil <= 16) {
         if (relu_in)
-            hipLaunchKernelGGL((k_conv_col<true, false, false, false, true>), dim3(col_groups(dil, 1, H, W)), dim3(256),
+            hipLaunchKernelGGL((k_conv_col<true, false, false, false, true>), dim3(col_groups(dil, 1, H, W)), dim3(64 * kColRW),
                                0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
         else
             hipLaunchKernelGGL((k_conv_col<false, false, false, false, true>), dim3(col_groups(dil, 1, H, W)),
-                               dim3(256), 0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+                               dim3(64 * kColRW), 0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
         return hipGetLastError();
     }
     const long long segs = (long long)H * ((W + 31) / 32);
