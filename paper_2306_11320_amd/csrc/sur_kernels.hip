@@ -239,9 +239,9 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
 // taps then take the zero weight block) are staged once in LDS over the
 // column's window of 32 + 2d pixels (periodic in x), with the ReLU applied as
 // they are staged, and the 18 operands of each segment are read from there:
-// each input pixel is loaded ~1.25 times per segment instead of 9 times.  Pixels are padded to
-// 80 bytes, so a wave's operand reads meet distinct banks.  The products and
-// their order are those of k_conv.
+// each input pixel is loaded ~1.25 times per segment instead of 9 times.
+// Pixels are padded to 80 bytes, so a wave's operand reads meet distinct
+// banks.  The products and their order are those of k_conv.
 constexpr int kColPix = 64, kColPS = 40;
 // Output rows (waves) per workgroup: eight (ten staged rows, 70 KB of LDS, two
 // workgroups and 4 waves per SIMD) measured 12-14% faster per network block
@@ -279,10 +279,10 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
         if (y0 >= H) continue;  // the same for the whole workgroup
         const int x0 = sx * 32;
         __syncthreads();  // every wave is done with the previous item's rows
-        // one row per pass: work-item (i, c) = (tid / 4, tid % 4) takes channels
-        // 8c .. 8c + 7 of window pixel i (win <= 64 pixels, 4 chunks each)
-        // (work-items beyond the window load its last pixel and store nothing)
-        // (RW / 4 rows per pass: work-item t takes row t / 256 of the pass)
+        // RW / 4 rows per pass: work-item t takes row t / 256 of the pass and
+        // channels 8c .. 8c + 7 of window pixel i, (i, c) = ((t % 256) / 4, t % 4)
+        // (win <= 64 pixels of 4 chunks; work-items beyond the window load its
+        // last pixel and store nothing)
         constexpr int RP = RW / 4, NPASS = (kColRows + RP - 1) / RP;
         const int c = threadIdx.x % 4, i = (threadIdx.x % 256) / 4, jr = threadIdx.x / 256;
         int xx = x0 - dil + (i < win ? i : win - 1);
