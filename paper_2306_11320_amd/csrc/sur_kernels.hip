@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) void k_frame_final(const double* __restrict__ 
 
 // ---- launchers ----
 
-// Workgroups of a column-kernel launch: every column's group of four rows of
+// Workgroups of a column-kernel launch: every column's group of kColRW rows of
 // one residue class of y mod dil is one work item.
 static unsigned col_groups(int dil, int N, int H, int W)
 {
@@ -679,8 +679,8 @@ static void conv_t(const bf16* in, const bf16* w, const float* bias, const void*
                    int dil, int N, int H, int W, hipStream_t s)
 {
     if (CIN == 32 && dil <= 16) {
-        // by columns: a resident grid (three workgroups per CU) walks the
-        // columns' groups of four rows
+        // by columns: a resident grid (two workgroups per CU) walks the
+        // columns' groups of rows
         hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W)), dim3(64 * kColRW), 0, s, in,
                            w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
         return;
