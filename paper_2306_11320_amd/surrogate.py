@@ -369,13 +369,29 @@ class Surrogate:
 
 # ---- data from the lattice Boltzmann update --------------------------------
 
+def _tuned_batch(items, device):
+    """The batched FP32 lattice of `items` with the autotuner's launch
+    configuration, chosen on a throwaway copy (trial steps advance the state
+    they run on; the choice does not change the results, which are bitwise
+    independent of the tile shape and grid)."""
+    probe = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    try:
+        tuned = probe.autotune(steps_per_trial=4)
+    finally:
+        probe.close()
+    lat = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    lat.set_tile(tuned["tile"])
+    lat.set_grid(tuned["grid"])
+    return lat
+
+
 def generate_pairs(items, K: int, starts, device="cuda:0"):
     """Runs the batched FP32 lattice update over `items` (all of one size) and
     returns network inputs X (BF16 [P, H, W, 8]) and target increments Y (FP32
     [P, H, W, N_OUT], in units of (1, U, U, dT, P)) of the states K steps
     later, for every start time in `starts` and every lattice."""
     import torch
-    lat = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    lat = _tuned_batch(items, device)
     ny, nx = lat.shapes[0]
     n = len(items)
     P = n * len(starts)
@@ -408,7 +424,7 @@ def generate_pairs_uneven(items, K: int, starts, device="cuda:0"):
     step): returns per-lattice lists Xs[l] (BF16 [S, H_l, W_l, 8]) and Ys[l]
     (FP32 [S, H_l, W_l, N_OUT]), S = len(starts)."""
     import torch
-    lat = _lbm.Lattice.batch(items, _lbm.FP32_DEV, device=device)
+    lat = _tuned_batch(items, device)
     n = len(items)
     S = len(starts)
     Xs = [torch.empty((S, ny, nx, 8), dtype=torch.bfloat16, device=device) for ny, nx in lat.shapes]

@@ -333,6 +333,40 @@ def test_conv_advance_fused(relu_in, dil, W, stream):
         assert np.abs(got - want).max() <= 1e-5 * (np.abs(want).max() + 1.0), k
 
 
+def test_generate_pairs_uneven_equals_single_lattices():
+    """Training pairs from the batched generator (autotuned launch on lattices
+    of uneven size) equal, bitwise, the pairs built from each lattice stepped
+    on its own: states at the start times and their increments K steps later."""
+    from paper_2306_11320_amd import lbm, workloads as wl
+    announce("generate_pairs_uneven")
+    items = wl.sweep(3, seed=9, nx_range=(64, 96), laplace_p=True)
+    K, starts = 10, [20, 40]
+    Xs, Ys = sur.generate_pairs_uneven(items, K, starts)
+    for k, (cfg, f0) in enumerate(items):
+        lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+        sc = sur.scales_of(cfg)
+        st = lat.stream
+        ny, nx = lat.shapes[0]
+        a = {key: torch.empty((ny, nx), device="cuda") for key in sur.FIELDS}
+        b = {key: torch.empty((ny, nx), device="cuda") for key in sur.FIELDS}
+        x = torch.empty((ny, nx, 8), dtype=torch.bfloat16, device="cuda")
+        y = torch.empty((ny, nx, sur.N_OUT), device="cuda")
+        torch.cuda.synchronize()
+        t = 0
+        for q, s0 in enumerate(starts):
+            lat.step(s0 - t)
+            lat.fields(0, out="f32", into=a)
+            sur.sur_pack(a, sc, x, st)
+            lat.step(K)
+            t = s0 + K
+            lat.fields(0, out="f32", into=b)
+            sur.sur_pack_target(a, b, sc, y, st)
+            st.synchronize()
+            assert torch.equal(Xs[k][q].view(torch.int16), x.view(torch.int16)), (k, q)
+            assert torch.equal(Ys[k][q], y), (k, q)
+        lat.close()
+
+
 def test_light_volume_and_judge(stream):
     announce("volume_judge")
     rng = np.random.default_rng(22)
