@@ -18,7 +18,8 @@ chosen by the autotuner.  The same JSON line also carries:
   window from the initial state (three lattices of the sweep);
 * the learned surrogate (trained on 2000 trajectories of the batched-sweep
   generator) against the plain FP32 lattice update, on 256 x 1024 lattices
-  and on the generator's uneven lattices;
+  and on the generator's uneven lattices, and its convolution against the
+  BF16 dense peak;
 * the oracle on the host cores, all cores and one thread.
 Working-set bytes are reported next to every number.  --only times just the
 named workload and precision (profiling runs).  Every timed workload takes
@@ -299,6 +300,47 @@ def surrogate_leg(n: int, blocks: int = 10, warm: int = 30000, weights: str = "s
     }
 
 
+def conv_leg(reps: int = 50) -> dict:
+    """The surrogate's convolutions on one 256 x 1024 frame, timed with HIP
+    events on the network's stream: a hidden layer (32 channels, dilation 4,
+    input ReLU and residual, BF16 out) against the BF16 dense peak, and a
+    whole network block (packing, six layers, the fused state update)."""
+    import torch
+    from paper_2306_11320_amd import surrogate as S
+    from paper_2306_11320_amd.train_surrogate import sweep_items
+    net = S.Surrogate.load(os.path.join(ROOT, "paper_2306_11320_amd", "weights", "surrogate_k100_sweep2000.npz"))
+    st = torch.cuda.Stream()
+    net.stream = st
+    H, W = 1024, 256
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = (0.5 * torch.randn((1, H, W, 32), generator=g)).to(torch.bfloat16).to("cuda")
+    out = torch.empty_like(x)
+    cfg, _ = sweep_items(1, 55, W, H)[0]
+    sc = S.scales_of(cfg, net.kappa)
+    state = {k: torch.zeros((H, W), device="cuda") for k in S.FIELDS}
+    state["phi"].fill_(1.0)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        st.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    layer_us = timed(lambda: S.sur_conv3x3(x, 32, net.Wb[2], net.b[2], x, None, out, True, st, 4))
+    block_us = timed(lambda: net.advance(state, sc))
+    flop = 2 * 9 * 32 * 32 * H * W
+    return {"frame": "256x1024", "hidden_layer_us": round(layer_us, 2),
+            "hidden_layer_tflops": round(flop / layer_us / 1e6, 1),
+            "hidden_layer_frac_of_bf16_dense_peak": round(flop / layer_us / 1e6 / 2500.0, 4),
+            "network_block_us": round(block_us, 1), "flop_per_hidden_layer": flop}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,6 +445,7 @@ def main():
             # fixed 256 x 1024 lattices
             log("surrogate")
             out["surrogate"] = surrogate_leg(args.surrogate)
+            out["surrogate_conv"] = conv_leg()
             log("surrogate on lattices of the batched-sweep generator")
             out["surrogate_uneven"] = surrogate_leg(2, lattices="sweep")
             log("surrogate trained on 64 fixed lattices")
