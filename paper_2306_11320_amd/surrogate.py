@@ -575,14 +575,21 @@ class Hybrid:
     trigger, or a light-phase volume drift above `tol_vol` since the start,
     hands the following `fallback_blocks` blocks to the lattice update, which
     continues from its judged result; otherwise the network's state
-    continues."""
+    continues.
+
+    With graph=True the run of check_every - 1 network blocks between judged
+    blocks (packing, six layers and the volume reduction per block) is
+    captured once per state buffer into a HIP graph and replayed: one launch
+    instead of ~8 per block.  The graph holds the network's weights and
+    buffers as they were at capture: load other weights into the network, or
+    use it on a lattice of another size, only through a new Hybrid."""
 
     TRIGGER = (0, 3)            # phi, T
     TRIGGER_U = (1, 2)          # ux, uy
 
     def __init__(self, net: Surrogate, lat, cfg: dict, K: int = 100, check_every: int = 10,
                  tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None,
-                 tol_check_u: float = 0.03):
+                 tol_check_u: float = 0.03, graph: bool = True):
         import torch
         if net.stream is not lat.stream:
             raise ValueError("the network must run on the lattice's stream")
@@ -610,6 +617,46 @@ class Hybrid:
                           max_judge_u=0.0, max_drift=0.0, judge_errors=[])
         self.lat_current = True     # the lattice holds self.s
         self.fallback_left = 0
+        self.graph = bool(graph)
+        self._torch = torch
+        self._graphs = {}           # state buffer (phi's address) -> (graph, tensors it reads or writes)
+        if self.graph and self.C > 1:
+            # captured here, outside any timing; the other buffer's graph on its first use (after a fallback)
+            self._graphs[self.s["phi"].data_ptr()] = self._capture(self.C - 1)
+
+    def _net_run(self, n: int):
+        """n network blocks on self.s; the light-phase volume after block i
+        into self.vol[i]."""
+        st = self.lat.stream
+        if self.graph and n == self.C - 1:
+            key = self.s["phi"].data_ptr()
+            g = self._graphs.get(key)
+            if g is None:
+                g = self._graphs[key] = self._capture(n)
+            with self._torch.cuda.stream(st):      # replay() launches on the current stream
+                g[0].replay()
+            return
+        for i in range(n):
+            self.net.advance(self.s, self.sc)
+            sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
+
+    def _capture(self, n: int):
+        import torch
+        st = self.lat.stream
+        # first-call work (the network's buffers) outside the capture, on a copy
+        with torch.cuda.stream(st):
+            tmp = {k: v.clone() for k, v in self.s.items()}
+        self.net.advance(tmp, self.sc)
+        sur_light_volume(tmp["phi"], self.part, self.vol[:1], st)
+        st.synchronize()
+        del tmp
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            for i in range(n):
+                self.net.advance(self.s, self.sc)
+                sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
+        keep = [*self.s.values(), self.part, self.vol, *self.net._buf.values(), *self.net.Wb, *self.net.b]
+        return g, keep
 
     def _lbm_block(self, lat_current: bool):
         if not lat_current:
@@ -632,11 +679,10 @@ class Hybrid:
                 b += 1
                 continue
             n_net = min(self.C - 1, blocks - b - 1)
-            for i in range(n_net):
-                self.net.advance(self.s, self.sc)
-                sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
+            if n_net:
+                self._net_run(n_net)
                 lat_current = False
-                self.stats["net_blocks"] += 1
+                self.stats["net_blocks"] += n_net
             b += n_net
             # judged block: the lattice update and the network from one state
             if not lat_current:

@@ -428,6 +428,45 @@ def test_hybrid_bookkeeping():
         L.close()
 
 
+def test_hybrid_graph_replay_equals_eager():
+    """The network blocks between judged blocks replayed from a captured HIP
+    graph give bitwise the state, volumes and judged errors of the same blocks
+    launched one by one: undisturbed (four replays, with the judged blocks'
+    own launches and synchronisations between them) and with every judged
+    block falling back, so that the state buffers swap and the second buffer's
+    graph is captured on its first use."""
+    import os
+    from paper_2306_11320_amd import lbm, workloads as wl
+    announce("hybrid_graph_replay")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = sur.Surrogate.load(os.path.join(root, "paper_2306_11320_amd", "weights", "surrogate_k100_sweep2000.npz"))
+    cfg, f0 = wl.sweep_instance(96, 256, 12.0, 3.0, 1.5, laplace_p=True)
+    for kw, runs in ((dict(check_every=4, tol_check=1e9, tol_vol=1e9, tol_check_u=1e9), 4),
+                     (dict(check_every=3, tol_check=0.0, fallback_blocks=1), 3)):
+        # 4 blocks a run: 3 network + 1 judged, or 2 network (graph) + 1 judged (falls back) + 1 lattice
+        hs, lats = [], []
+        for graph in (False, True):
+            lat = lbm.Lattice(cfg, f0, lbm.FP32_DEV)
+            lat.step(200)
+            net.stream = lat.stream
+            hs.append(sur.Hybrid(net, lat, cfg, K=100, **kw, graph=graph))
+            lats.append(lat)
+        for r in range(runs):
+            for h in hs:
+                h.net.stream = h.lat.stream
+                h.run(4)
+            e, g = hs
+            for k in sur.FIELDS:
+                assert torch.equal(e.s[k], g.s[k]), (kw, r, k)
+            assert torch.equal(e.vol, g.vol), (kw, r)
+            assert e.stats["judge_errors"] == g.stats["judge_errors"], (kw, r)
+            assert (e.stats["net_blocks"], e.stats["fallbacks"]) == (g.stats["net_blocks"], g.stats["fallbacks"])
+        assert len(hs[1]._graphs) == (1 if kw["tol_check"] > 1 else 2)
+        assert hs[0].stats["fallbacks"] == (0 if kw["tol_check"] > 1 else runs)
+        for L in lats:
+            L.close()
+
+
 def test_trained_network_gain():
     """The earlier network, trained on 64 fixed 256 x 1024 lattices
     (weights/surrogate_k100.npz), against the plain FP32 lattice update on
