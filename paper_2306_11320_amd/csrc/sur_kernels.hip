@@ -242,7 +242,14 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
 // each input pixel is loaded ~1.25 times per segment instead of 9 times.
 // Pixels are padded to 80 bytes, so a wave's operand reads meet distinct
 // banks.  The products and their order are those of k_conv.
-constexpr int kColPix = 64, kColPS = 40;
+// The staged window holds up to kColPix pixels (dilation <= 16), or
+// kColPixNarrow for dilation <= 4: 51 KB of LDS instead of 70 KB, so three
+// workgroups fit a CU (6 waves per SIMD where the kernel holds <= 80 VGPRs).
+// Measured at 256 x 1024: the hidden layers with dilation 1, 2 and 4 take
+// 4-8% less time with the narrow window and a grid of three workgroups per CU
+// (768, unevenly loaded: 1024 column groups); a grid of 512 that loads every
+// workgroup evenly takes the wide window's time.
+constexpr int kColPix = 64, kColPixNarrow = 40, kColPS = 40;
 // Output rows (waves) per workgroup: eight (ten staged rows, 70 KB of LDS, two
 // workgroups and 4 waves per SIMD) measured 12-14% faster per network block
 // than four (six staged rows, 50 KB, three workgroups, 3 waves per SIMD).
@@ -251,7 +258,7 @@ constexpr int kColRows = kColRW + 2;
 
 // ADV: the output layer of inference, whose epilogue adds the increment to the
 // five state fields f (as k_conv_advance; N = 1).
-template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false>
+template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false, int PIX = kColPix>
 __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                                           const float* __restrict__ bias, const void* __restrict__ res,
                                                           const bf16* __restrict__ mask, void* __restrict__ out,
@@ -262,9 +269,9 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int m = lane % 32, kh = lane / 32, co = lane % 32;
     __shared__ bf16x8 sB[NKB + 1][64];
-    __shared__ __attribute__((aligned(16))) bf16 sX[kColRows][kColPix][kColPS];
+    __shared__ __attribute__((aligned(16))) bf16 sX[kColRows][PIX][kColPS];
     // ADV: per-wave transposition tile of the five state channels (16 pixels)
-    __shared__ float sT[ADV ? RW : 1][16][8];
+    __shared__ float sT[ADV ? RW : 1][16][5];
     stage_weights<32>(w, sB);
     const float bv = bias ? bias[co] : 0.f;
     const int SC = (W + 31) / 32;
@@ -281,8 +288,8 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
         __syncthreads();  // every wave is done with the previous item's rows
         // RW / 4 rows per pass: work-item t takes row t / 256 of the pass and
         // channels 8c .. 8c + 7 of window pixel i, (i, c) = ((t % 256) / 4, t % 4)
-        // (win <= 64 pixels of 4 chunks; work-items beyond the window load its
-        // last pixel and store nothing)
+        // (win <= PIX <= 64 pixels of 4 chunks; work-items beyond the window
+        // load its last pixel and store nothing)
         constexpr int RP = RW / 4, NPASS = (kColRows + RP - 1) / RP;
         const int c = threadIdx.x % 4, i = (threadIdx.x % 256) / 4, jr = threadIdx.x / 256;
         int xx = x0 - dil + (i < win ? i : win - 1);
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
             }
             if constexpr (ADV) {
                 // lane l < 32 takes pixel x0 + l of the five state channels
-                float (*T)[8] = sT[wave];
+                float (*T)[5] = sT[wave];
                 float v[5];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -667,10 +674,11 @@ __global__ __launch_bounds__(256) void k_frame_final(const double* __restrict__ 
 
 // Workgroups of a column-kernel launch: every column's group of kColRW rows of
 // one residue class of y mod dil is one work item.
-static unsigned col_groups(int dil, int N, int H, int W)
+// per_cu: resident workgroups per CU (bound by LDS).
+static unsigned col_groups(int dil, int N, int H, int W, int per_cu)
 {
     const long long items = (long long)N * dil * (((H + dil - 1) / dil + kColRW - 1) / kColRW) * ((W + 31) / 32);
-    const long long cap = 256 * (kColRW == 4 ? 3 : 2);  // resident workgroups (bound by LDS)
+    const long long cap = 256LL * per_cu;
     return (unsigned)(items < cap ? items : cap);
 }
 
@@ -678,11 +686,17 @@ template <int CIN, bool RELU, bool OUTF32, bool RES, bool MASK>
 static void conv_t(const bf16* in, const bf16* w, const float* bias, const void* res, const bf16* mask, void* out,
                    int dil, int N, int H, int W, hipStream_t s)
 {
-    if (CIN == 32 && dil <= 16) {
-        // by columns: a resident grid (two workgroups per CU) walks the
+    if (CIN == 32 && dil <= 4) {
+        // by columns: a resident grid (three workgroups per CU) walks the
         // columns' groups of rows
-        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W)), dim3(64 * kColRW), 0, s, in,
-                           w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
+        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK, false, kColPixNarrow>), dim3(col_groups(dil, N, H, W, 3)),
+                           dim3(64 * kColRW), 0, s, in, w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
+        return;
+    }
+    if (CIN == 32 && dil <= 16) {
+        // the same with the wide window (two workgroups per CU)
+        hipLaunchKernelGGL((k_conv_col<RELU, OUTF32, RES, MASK>), dim3(col_groups(dil, N, H, W, 2)), dim3(64 * kColRW), 0, s,
+                           in, w, bias, res, mask, out, dil, N, H, W, State5{}, Scales{});
         return;
     }
     // a resident grid (6 waves per SIMD on 256 CUs) walks the segments, so
@@ -722,16 +736,23 @@ hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const
     return hipGetLastError();
 }
 
+// The output layer by columns (dilation <= 16) keeps the wide window and two
+// workgroups per CU: with the narrow one and three per CU it was slower
+// (11.6 against 10.2 us at 256 x 1024, dilation 1).
+template <bool RELU>
+static void col_advance(const bf16* in, const bf16* w, const float* bias, int dil, int H, int W, const Scales& sc,
+                        const State5& f, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_conv_col<RELU, false, false, false, true>), dim3(col_groups(dil, 1, H, W, 2)), dim3(64 * kColRW),
+                       0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+}
+
 hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
                         const Scales& sc, const State5& f, hipStream_t s)
 {
     if (dil <= 16) {
-        if (relu_in)
-            hipLaunchKernelGGL((k_conv_col<true, false, false, false, true>), dim3(col_groups(dil, 1, H, W)), dim3(64 * kColRW),
-                               0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
-        else
-            hipLaunchKernelGGL((k_conv_col<false, false, false, false, true>), dim3(col_groups(dil, 1, H, W)),
-                               dim3(64 * kColRW), 0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+        if (relu_in) col_advance<true>(in, w, bias, dil, H, W, sc, f, s);
+        else col_advance<false>(in, w, bias, dil, H, W, sc, f, s);
         return hipGetLastError();
     }
     const long long segs = (long long)H * ((W + 31) / 32);
