@@ -89,6 +89,29 @@ def test_conv_forward(cin, relu_in, dil, W, stream):
     assert np.all(np.abs(got - refb) <= 2 ** -7 * np.abs(refb) + 1e-6)
 
 
+@pytest.mark.parametrize("dil", [2, 4, 5, 8])
+def test_conv_columns_many_items(dil, stream):
+    """The hidden layer as the network runs it (ReLU on the input, the input as
+    a BF16 residual, BF16 output) on 8 frames of 128 x 256: more column groups
+    than resident workgroups, so each workgroup walks several of them; on
+    both sides of the switch between the 40-pixel staging window (dilation
+    <= 4, three workgroups per CU) and the 64-pixel one.  Within one BF16 step
+    of the reference rounded to BF16."""
+    rng = np.random.default_rng(40 + dil)
+    N, H, W = 8, 128, 256
+    announce("conv_columns_many_items", dil)
+    x = cr.bf16_round(rng.standard_normal((N, H, W, 32)))
+    w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, 32)))
+    b = rng.standard_normal(32).astype(np.float32)
+    xd, wd, bd = dev(stream, t_bf16(x), t_bf16(w), t_f32(b))
+    out = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
+    sur.sur_conv3x3(xd, 32, wd, bd, xd, None, out, True, stream, dil)
+    stream.synchronize()
+    ref = cr.bf16_round(cr.conv(cr.relu(x), w, b, dil) + x)
+    got = host(out)
+    assert np.all(np.abs(got - ref) <= 2 ** -7 * np.abs(ref) + 1e-6)
+
+
 def test_adjoint_input_gradient(stream):
     rng = np.random.default_rng(7)
     N, H = 1, 6
