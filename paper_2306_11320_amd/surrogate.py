@@ -591,6 +591,7 @@ class Hybrid:
                  tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None,
                  tol_check_u: float = 0.03, graph: bool = True):
         import torch
+        self._torch = torch
         if net.stream is not lat.stream:
             raise ValueError("the network must run on the lattice's stream")
         if check_every < 1:
@@ -606,8 +607,11 @@ class Hybrid:
         self.s = {k: torch.empty((ny, nx), device=dev) for k in FIELDS}
         self.s_lbm = {k: torch.empty((ny, nx), device=dev) for k in FIELDS}
         self.part = torch.empty(8 * 256, dtype=torch.float64, device=dev)
-        self.vol = torch.zeros(self.C + 1, dtype=torch.float64, device=dev)
-        self.judge_out = torch.empty(8, dtype=torch.float64, device=dev)
+        # the judge's sums, then the light-phase volumes after each network block (and at the start, last):
+        # one buffer, read back by one copy into pinned memory per judged block
+        self.red = torch.zeros(8 + self.C + 1, dtype=torch.float64, device=dev)
+        self.judge_out, self.vol = self.red[:8], self.red[8:]
+        self.red_host = torch.empty(8 + self.C + 1, dtype=torch.float64, pin_memory=True)
         lat.set_graph_steps(self.K)
         lat.fields(0, out="f32", into=self.s)
         sur_light_volume(self.s["phi"], self.part, self.vol[self.C:], lat.stream)
@@ -618,7 +622,6 @@ class Hybrid:
         self.lat_current = True     # the lattice holds self.s
         self.fallback_left = 0
         self.graph = bool(graph)
-        self._torch = torch
         self._graphs = {}           # state buffer (phi's address) -> (graph, tensors it reads or writes)
         if self.graph and self.C > 1:
             # captured here, outside any timing; the other buffer's graph on its first use (after a fallback)
@@ -691,16 +694,18 @@ class Hybrid:
             self.lat.fields(0, out="f32", into=self.s_lbm)
             self.net.advance(self.s, self.sc)
             sur_judge(self.s, self.s_lbm, self.sc, self.part, self.judge_out, st)
+            with self._torch.cuda.stream(st):
+                self.red_host.copy_(self.red, non_blocking=True)
             self.stats["judged"] += 1
             self.stats["lbm_blocks"] += 1
             b += 1
             st.synchronize()
-            j = self.judge_out.cpu().numpy()
+            j = self.red_host[:8].numpy()
             err = [math.sqrt(j[2 * c] / j[2 * c + 1]) if j[2 * c + 1] > 0 else math.sqrt(j[2 * c]) for c in range(4)]
             self.stats["judge_errors"].append(err)
             drift = 0.0
             if n_net:
-                vols = self.vol[:n_net].cpu().numpy()
+                vols = self.red_host[8:8 + n_net].numpy()
                 drift = float(np.max(np.abs(vols - self.vol0)) / self.vol0)
             trig = max(err[c] for c in self.TRIGGER)
             trig_u = max(err[c] for c in self.TRIGGER_U)
