@@ -6,8 +6,12 @@ unmodified oracle passes the same pin (the pins' own tests).
 Planted mistakes: a dropped factor 1/2 in the parabolic term of Eq. 63, T_ref
 dropped from sigma'(T), a sign error in sigma'(T), the farthest centroid in
 place of the nearest one in the region split of Sec. 4.3, ties sent to the
-higher region, a region's x centroid summed over y, and, for Adam, a missing
-bias correction, swapped decay rates and a bias correction one step late.
+higher region, a region's x centroid summed over y; for the channel of Sec.
+4.3, the inflow profile scaled by 4 instead of 6, the inflow velocity with the
+wrong sign, an outlet that copies the node's own post-collision population
+(a zero-gradient reading) and an outlet that bounces back like a wall; and,
+for Adam, a missing bias correction, swapped decay rates and a bias
+correction one step late.
 """
 import os
 
@@ -17,6 +21,7 @@ import pytest
 import oracle
 from oracle import conv_ref as cr
 from tests import test_oracle_conv as tconv
+from tests import test_oracle_pins as tpins
 from tests import test_oracle_sigma_regions as tsr
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "lbm_oracle.c")).read()
@@ -34,6 +39,14 @@ MUTANTS = {
                        [tsr.test_regions_tie_and_empty_region, tsr.test_regions_split_equidistant_column]),
     "region_x_from_y": ("bxs[best] += phi * i;", "bxs[best] += phi * j;",
                         [lambda: tsr.test_regions_two_static_drops((0, 1))]),
+    "inflow_profile_scale": ("double un = 6.0 * P->u_in", "double un = 4.0 * P->u_in",
+                             [tpins.check_channel_flow]),
+    "inflow_sign": ("gb = gs[k] - 2.0 * WI[k] * rho", "gb = gs[k] + 2.0 * WI[k] * rho",
+                    [tpins.check_channel_flow]),
+    "outlet_copy": ("gb = -gs[k] + 2.0 * WI[k] * rho * (cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));",
+                    "gb = gs[kb] + 0.0 * rho * cu * uu;", [tpins.check_channel_flow]),
+    "outlet_closed": ("gb = -gs[k] + 2.0 * WI[k] * rho * (cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));",
+                      "gb = gs[k] + 0.0 * rho * cu * uu;", [tpins.check_channel_flow]),
 }
 
 
