@@ -480,24 +480,29 @@ def test_every_slot_written_once(bcs):
         assert (cnt == 1).all(), np.argwhere(cnt != 1)[:5]
 
 
-def check_channel_flow():
-    """Steady single-phase channel with the bubble case's boundaries (Sec. 4.3:
-    fully developed inflow, stress-free outlet, adiabatic walls), 16 wide and
-    48 long, u_ave = 1e-3, mu = 0.1.  Continuity fixes the volume flux through
-    every row, the outlet row included, at the inflow's u_ave H (within 1e-3);
-    the plane Poiseuille solution of the Navier-Stokes equations fixes the
-    pressure gradient at -12 mu u_ave / H^2 (within 1 % mid-channel, rows
-    12-35, uniform across the channel); the outlet holds the pressure level:
-    the field is stationary (2000 more steps change p by < 1e-8) and the
-    outlet row's pressure lies within two rows' worth of the gradient of zero."""
-    nx, ny, u, mu = 16, 48, 1e-3, 0.1
-    p = single_phase(nx, ny, bc=[wl.WALL_ADIABATIC, wl.WALL_ADIABATIC, wl.INLET, wl.OUTLET], mu_h=mu, mu_l=mu,
-                     u_in_mean=u, phi_in=1.0)
-    o = oracle.Oracle(p, fields(np.ones((ny, nx)), T=np.zeros((ny, nx))))
-    o.step(8000)
-    F0 = o.fields()
-    o.step(2000)
-    F = o.fields()
+CHANNEL = dict(nx=16, ny=48, u=1e-3, mu=0.1)
+
+
+def channel_case():
+    """Single-phase channel with the bubble case's boundaries (Sec. 4.3: fully
+    developed inflow at y = 0, stress-free outlet at y = ny, adiabatic walls in
+    x), 16 wide and 48 long, u_ave = 1e-3, mu = 0.1, at rest at the start."""
+    nx, ny = CHANNEL["nx"], CHANNEL["ny"]
+    p = single_phase(nx, ny, bc=[wl.WALL_ADIABATIC, wl.WALL_ADIABATIC, wl.INLET, wl.OUTLET], mu_h=CHANNEL["mu"],
+                     mu_l=CHANNEL["mu"], u_in_mean=CHANNEL["u"], phi_in=1.0)
+    return p, fields(np.ones((ny, nx)), T=np.zeros((ny, nx)))
+
+
+def check_channel_fields(F0, F):
+    """F0 and F: fields of the channel after 8000 and 10000 steps.  Continuity
+    fixes the volume flux through every row, the outlet row included, at the
+    inflow's u_ave H (within 1e-3); the plane Poiseuille solution of the
+    Navier-Stokes equations fixes the pressure gradient at -12 mu u_ave / H^2
+    (within 1 % mid-channel, rows 12-35, uniform across the channel); the
+    outlet holds the pressure level: the field is stationary (the last 2000
+    steps change p by < 1e-8) and the outlet row's pressure lies within two
+    rows' worth of the gradient of zero."""
+    nx, ny, u, mu = CHANNEL["nx"], CHANNEL["ny"], CHANNEL["u"], CHANNEL["mu"]
     flux = F["uy"].sum(axis=1) / (u * nx)
     assert np.all(np.isfinite(flux)) and np.abs(flux - 1.0).max() < 1e-3, flux
     grad = -12.0 * mu * u / nx ** 2
@@ -508,6 +513,16 @@ def check_channel_flow():
     assert np.abs(F["p"][12:36] - pm[12:36, None]).max() < 1e-3 * abs(grad) * ny
     assert np.abs(F["p"] - F0["p"]).max() < 1e-8
     assert abs(pm[-1]) < 2.0 * abs(grad)
+
+
+def check_channel_flow():
+    """The oracle's steady channel meets check_channel_fields."""
+    p, f0 = channel_case()
+    o = oracle.Oracle(p, f0)
+    o.step(8000)
+    F0 = o.fields()
+    o.step(2000)
+    check_channel_fields(F0, o.fields())
 
 
 def test_channel_continuity_and_poiseuille_pressure():
