@@ -671,6 +671,8 @@ class Hybrid:
     def run(self, blocks: int) -> dict:
         """Advances `blocks` blocks (calls may follow one another)."""
         st = self.lat.stream
+        if self.net.stream is not st:
+            raise ValueError("the network must run on the lattice's stream")
         lat_current = self.lat_current
         fallback_left = self.fallback_left
         b = 0
