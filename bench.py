@@ -22,7 +22,8 @@ chosen by the autotuner.  The same JSON line also carries:
   BF16 dense peak;
 * the oracle on the host cores, all cores and one thread.
 Working-set bytes are reported next to every number.  --only times just the
-named workload and precision (profiling runs).  Every timed workload takes
+named workload and precision, --conv-only just the surrogate's convolution
+timings (profiling runs).  Every timed workload takes
 the autotuner's tile (and, for batches, grid) choice.  Only one GPU is used;
 --gpus above 1 is refused.
 """
@@ -358,6 +359,8 @@ def main():
                     help="lattices for the surrogate leg (0 skips it)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate leg on --surrogate lattices (profiling runs)")
+    ap.add_argument("--conv-only", action="store_true",
+                    help="run only the surrogate's convolution timings (profiling runs)")
     ap.add_argument("--potential", action="store_true",
                     help="potential form of the capillary force (-phi grad mu_phi) instead of Eq. 11's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -389,6 +392,9 @@ def main():
         ms = e0.elapsed_time(e1) / 20
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": ms,
                           "copy_GBps": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
+    if args.conv_only:
+        print(json.dumps({"surrogate_conv": conv_leg()}), flush=True)
         return
     prewarm()
     if args.surrogate_only:
