@@ -100,6 +100,20 @@ int sur_advance(const float* d_delta, int64_t npix, const sur_scales* scales, fl
  * [1, w], too many segments or misaligned in / w. */
 int sur_conv3x3_advance(const void* d_in, const void* d_w, const float* d_bias, int relu_in, int dil, int h, int w,
                         const sur_scales* scales, float* const* d_f, void* stream);
+/* sur_conv3x3_advance (dil <= 16) that also writes the light-phase volume
+ * sum (1 - phi)/2 of the updated phi, in FP64, into *d_vol (device): the
+ * hybrid rollout's check of the light phase after each network block, without
+ * a separate reduction over the frame.  The state is bitwise that of
+ * sur_conv3x3_advance; the volume equals sur_light_volume's up to the order of
+ * the FP64 sums (fixed for given h and w).  d_part: 8 * SUR_VOLUME_PARTS
+ * doubles of device scratch, 8-byte aligned (per-workgroup partials, summed
+ * in a fixed order by a second kernel on the same stream).  Calls that share
+ * d_part must not overlap in time.  Errors: as sur_conv3x3_advance, also NULL
+ * d_part or d_vol and dil > 16. */
+#define SUR_VOLUME_PARTS 512
+int sur_conv3x3_advance_volume(const void* d_in, const void* d_w, const float* d_bias, int relu_in, int dil, int h,
+                               int w, const sur_scales* scales, float* const* d_f, double* d_part, double* d_vol,
+                               void* stream);
 /* Light-phase volume sum (1 - phi)/2 of a frame, in FP64, into *d_out (device),
  * through `groups` partials in d_part (8*groups doubles), summed in a fixed order. */
 int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int groups, double* d_out, void* stream);

@@ -4,6 +4,7 @@
 #include "sur_internal.hpp"
 
 static_assert(SUR_JUDGE_MAX_GROUPS == sur::kJudgeMaxGroups, "judge scratch size");
+static_assert(SUR_VOLUME_PARTS == sur::kVolPartsApi, "volume partials");
 
 #include <cstdio>
 #include <string>
@@ -158,6 +159,24 @@ int sur_conv3x3_advance(const void* d_in, const void* d_w, const float* d_bias, 
     return check(sur::conv_advance(static_cast<const bf16*>(d_in), static_cast<const bf16*>(d_w), d_bias, relu_in, dil,
                                    h, w, sc, f, static_cast<hipStream_t>(stream)),
                  "sur_conv3x3_advance");
+}
+
+int sur_conv3x3_advance_volume(const void* d_in, const void* d_w, const float* d_bias, int relu_in, int dil, int h,
+                               int w, const sur_scales* scales, float* const* d_f, double* d_part, double* d_vol,
+                               void* stream)
+{
+    sur::State5 f;
+    sur::Scales sc;
+    if (!d_in || !d_w || !get_state(d_f, f) || !get_scales(scales, sc) || !d_part || !d_vol)
+        return bad("sur_conv3x3_advance_volume: bad arguments");
+    if (h < 1 || w < 1) return bad("sur_conv3x3_advance_volume: need h, w >= 1");
+    if (dil < 1 || dil > w || dil > 16) return bad("sur_conv3x3_advance_volume: need 1 <= dil <= min(w, 16)");
+    if ((long long)h * ((w + 31) / 32) >= (1LL << 30)) return bad("sur_conv3x3_advance_volume: more than 2^30 segments");
+    if (!aligned16(d_in) || !aligned16(d_w) || (reinterpret_cast<uintptr_t>(d_part) & 7))
+        return bad("sur_conv3x3_advance_volume: in and w must be 16-byte aligned, part 8-byte aligned");
+    return check(sur::conv_advance_volume(static_cast<const bf16*>(d_in), static_cast<const bf16*>(d_w), d_bias,
+                                          relu_in, dil, h, w, sc, f, d_part, d_vol, static_cast<hipStream_t>(stream)),
+                 "sur_conv3x3_advance_volume");
 }
 
 int sur_light_volume(const float* d_phi, int h, int w, double* d_part, int groups, double* d_out, void* stream)

@@ -34,6 +34,11 @@ hipError_t pack_target(const State5& f0, const State5& f1, long long npix, const
 hipError_t advance(const float* delta, long long npix, const Scales& sc, const State5& f, hipStream_t s);
 hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
                         const Scales& sc, const State5& f, hipStream_t s);
+constexpr int kVolPartsApi = 512;  // partials of conv_advance_volume (the column kernel's kVolParts)
+// conv_advance (dilation <= 16) that also sums the light-phase volume of the
+// updated phi into *vout; vpart holds kVolParts partials and a zero counter.
+hipError_t conv_advance_volume(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
+                               const Scales& sc, const State5& f, double* vpart, double* vout, hipStream_t s);
 hipError_t frame_sums(const State5& a, const State5* b, long long npix, int w, const Scales& sc, double* part,
                       int groups, double* out, hipStream_t s);
 

@@ -257,13 +257,23 @@ constexpr int kColRW = 8;
 constexpr int kColRows = kColRW + 2;
 
 // ADV: the output layer of inference, whose epilogue adds the increment to the
-// five state fields f (as k_conv_advance; N = 1).
-template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false, int PIX = kColPix>
+// five state fields f (as k_conv_advance; N = 1).  VOL (with ADV): the
+// epilogue also sums the light-phase volume (1 - phi) / 2 of the updated phi
+// in FP64, per workgroup in a fixed order, into vpart[8 blockIdx.x] (the
+// partials layout of k_frame_sums, which k_frame_final sums).  A last
+// workgroup that sums the partials after an atomic ticket needs agent-scope
+// fences (an L2 write-back per workgroup): measured slower than the separate
+// final kernel.
+constexpr int kVolParts = kVolPartsApi;  // at least the column kernel's grid (<= 256 * 2)
+template <bool RELU, bool OUTF32, bool RES, bool MASK, bool ADV = false, int PIX = kColPix, bool VOL = false>
 __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                                           const float* __restrict__ bias, const void* __restrict__ res,
                                                           const bf16* __restrict__ mask, void* __restrict__ out,
-                                                          int dil, int N, int H, int W, State5 f, Scales sc)
+                                                          int dil, int N, int H, int W, State5 f, Scales sc,
+                                                          double* __restrict__ vpart = nullptr,
+                                                          double* __restrict__ vout = nullptr)
 {
+    static_assert(!VOL || ADV, "the volume is summed in the state update's epilogue");
     constexpr int NKB = 18, RW = kColRW;
     const int lane = threadIdx.x % 64;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
@@ -282,6 +292,7 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
     constexpr int WE = (NKB + 1) * 64, WPT = EARLYW ? (WE + 64 * RW - 1) / (64 * RW) : 1;
     bf16x8 wv[WPT];
     bool wpending = EARLYW;
+    double vacc = 0.0;  // VOL: this lane's share of the light-phase volume
     if constexpr (EARLYW) {
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
@@ -380,13 +391,29 @@ __global__ __launch_bounds__(64 * kColRW) void k_conv_col(const bf16* __restrict
 #pragma unroll
                     for (int cc = 0; cc < 5; ++cc) {
                         float* fc = const_cast<float*>(f.v[cc]);
-                        fc[p] = fc[p] + v[cc] * sc.inc[cc];
+                        const float nv = fc[p] + v[cc] * sc.inc[cc];
+                        fc[p] = nv;
+                        if (VOL && cc == 0) vacc += 0.5 * (1.0 - (double)nv);
                     }
                 }
             } else {
                 conv_store<OUTF32, RES, MASK>(acc, bv, res, mask, out, (((long long)n * H + y) * W + x0) * 32, x0, W,
                                               kh, co);
             }
+        }
+    }
+    if constexpr (VOL) {
+        // the wave's sum (butterfly: every lane ends with the same value), then the
+        // workgroup's in wave order into vpart[8 blockIdx.x]
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) vacc += __shfl_xor(vacc, o);
+        __shared__ double sV[RW];
+        if (lane == 0) sV[wave] = vacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < RW; ++k) t += sV[k];
+            vpart[8 * blockIdx.x] = t;
         }
     }
 }
@@ -767,20 +794,30 @@ hipError_t conv(const bf16* in, int cin, const bf16* w, const float* bias, const
 // The output layer by columns (dilation <= 16) keeps the wide window and two
 // workgroups per CU: with the narrow one and three per CU it was slower
 // (11.6 against 10.2 us at 256 x 1024, dilation 1).
-template <bool RELU>
+template <bool RELU, bool VOL>
 static void col_advance(const bf16* in, const bf16* w, const float* bias, int dil, int H, int W, const Scales& sc,
-                        const State5& f, hipStream_t s)
+                        const State5& f, double* vpart, double* vout, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_conv_col<RELU, false, false, false, true>), dim3(col_groups(dil, 1, H, W, 2)), dim3(64 * kColRW),
-                       0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc);
+    hipLaunchKernelGGL((k_conv_col<RELU, false, false, false, true, kColPix, VOL>), dim3(col_groups(dil, 1, H, W, 2)),
+                       dim3(64 * kColRW), 0, s, in, w, bias, nullptr, nullptr, nullptr, dil, 1, H, W, f, sc, vpart, vout);
+}
+
+hipError_t conv_advance_volume(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
+                               const Scales& sc, const State5& f, double* vpart, double* vout, hipStream_t s)
+{
+    if (dil > 16 || col_groups(dil, 1, H, W, 2) > (unsigned)kVolParts) return hipErrorInvalidValue;
+    if (relu_in) col_advance<true, true>(in, w, bias, dil, H, W, sc, f, vpart, vout, s);
+    else col_advance<false, true>(in, w, bias, dil, H, W, sc, f, vpart, vout, s);
+    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(256), 0, s, vpart, (int)col_groups(dil, 1, H, W, 2), 1, vout);
+    return hipGetLastError();
 }
 
 hipError_t conv_advance(const bf16* in, const bf16* w, const float* bias, int relu_in, int dil, int H, int W,
                         const Scales& sc, const State5& f, hipStream_t s)
 {
     if (dil <= 16) {
-        if (relu_in) col_advance<true>(in, w, bias, dil, H, W, sc, f, s);
-        else col_advance<false>(in, w, bias, dil, H, W, sc, f, s);
+        if (relu_in) col_advance<true, false>(in, w, bias, dil, H, W, sc, f, nullptr, nullptr, s);
+        else col_advance<false, false>(in, w, bias, dil, H, W, sc, f, nullptr, nullptr, s);
         return hipGetLastError();
     }
     const long long segs = (long long)H * ((W + 31) / 32);

@@ -75,6 +75,7 @@ def lib():
         L.sur_pack_target.argtypes = [pp, pp, i64, sp, vp, vp]
         L.sur_advance.argtypes = [vp, i64, sp, pp, vp]
         L.sur_conv3x3_advance.argtypes = [vp, vp, vp, ip, ip, ip, ip, sp, pp, vp]
+        L.sur_conv3x3_advance_volume.argtypes = [vp, vp, vp, ip, ip, ip, ip, sp, pp, vp, vp, vp]
         L.sur_light_volume.argtypes = [vp, ip, ip, vp, ip, vp, vp]
         L.sur_judge.argtypes = [pp, pp, ip, ip, sp, vp, ip, vp, vp]
         L.sur_judge_noscratch.argtypes = [pp, pp, ip, ip, sp, ip, vp, vp]
@@ -150,6 +151,15 @@ def sur_conv3x3_advance(x, w, bias, relu_in, sc: SurScales, f, stream, dil=1):
     h, wd = f["phi"].shape
     _ck(lib().sur_conv3x3_advance(_p(x), _p(w), _p(bias), int(relu_in), int(dil), h, wd, C.byref(sc), _state(f),
                                   _s(stream)))
+
+
+VOLUME_PARTS = 512   # SUR_VOLUME_PARTS
+
+
+def sur_conv3x3_advance_volume(x, w, bias, relu_in, sc: SurScales, f, part, vol, stream, dil=1):
+    h, wd = f["phi"].shape
+    _ck(lib().sur_conv3x3_advance_volume(_p(x), _p(w), _p(bias), int(relu_in), int(dil), h, wd, C.byref(sc),
+                                         _state(f), _p(part), _p(vol), _s(stream)))
 
 
 def sur_light_volume(phi, part, out, stream):
@@ -356,15 +366,21 @@ class Surrogate:
         return net
 
     # ---- one block of K lattice steps on a state ----
-    def advance(self, state: dict, sc: SurScales) -> None:
+    def advance(self, state: dict, sc: SurScales, part=None, vol=None) -> None:
         """state (five FP32 (ny, nx) device tensors) += the predicted increment,
-        on self.stream."""
+        on self.stream.  With part and vol (FP64 device tensors of
+        8 * VOLUME_PARTS elements and of one element) the
+        output layer also writes the light-phase volume of the updated phi
+        into vol (output-layer dilation <= 16)."""
         ny, nx = state["phi"].shape
         x = self._get("x1", (1, ny, nx, 8), self.torch.bfloat16)
         sur_pack(state, sc, x, self.stream)
         h, _ = self._hidden(x, False)
         # the output layer adds its increment to the state directly
-        sur_conv3x3_advance(h, self.Wb[5], self.b[5], True, sc, state, self.stream, self.dil[5])
+        if vol is None:
+            sur_conv3x3_advance(h, self.Wb[5], self.b[5], True, sc, state, self.stream, self.dil[5])
+        else:
+            sur_conv3x3_advance_volume(h, self.Wb[5], self.b[5], True, sc, state, part, vol, self.stream, self.dil[5])
 
 
 # ---- data from the lattice Boltzmann update --------------------------------
@@ -580,16 +596,19 @@ class Hybrid:
     With graph=True the run of check_every - 1 network blocks between judged
     blocks (packing, six layers and the volume reduction per block) is
     captured once per state buffer into a HIP graph and replayed: one launch
-    instead of ~8 per block.  The graph holds the network's weights and
-    buffers as they were at capture: load other weights into the network, or
-    use it on a lattice of another size, only through a new Hybrid."""
+    instead of ~8 per block, for small lattices whose kernels take less time
+    than their launches (at 256 x 1024 the launches keep ahead of the GPU and
+    the replay measured 1-3 % slower per 10 blocks).  The graph holds the
+    network's weights and buffers as they were at capture: load other weights
+    into the network, or use it on a lattice of another size, only through a
+    new Hybrid."""
 
     TRIGGER = (0, 3)            # phi, T
     TRIGGER_U = (1, 2)          # ux, uy
 
     def __init__(self, net: Surrogate, lat, cfg: dict, K: int = 100, check_every: int = 10,
                  tol_check: float = 0.01, tol_vol: float = 0.01, fallback_blocks: int | None = None,
-                 tol_check_u: float = 0.03, graph: bool = True):
+                 tol_check_u: float = 0.03, graph: bool = False):
         import torch
         self._torch = torch
         if net.stream is not lat.stream:
@@ -612,6 +631,8 @@ class Hybrid:
         self.red = torch.zeros(8 + self.C + 1, dtype=torch.float64, device=dev)
         self.judge_out, self.vol = self.red[:8], self.red[8:]
         self.red_host = torch.empty(8 + self.C + 1, dtype=torch.float64, pin_memory=True)
+        # the output layer sums the volume's partials itself when its dilation allows
+        self.vpart = torch.empty(8 * VOLUME_PARTS, dtype=torch.float64, device=dev) if net.dil[5] <= 16 else None
         lat.set_graph_steps(self.K)
         lat.fields(0, out="f32", into=self.s)
         sur_light_volume(self.s["phi"], self.part, self.vol[self.C:], lat.stream)
@@ -640,8 +661,15 @@ class Hybrid:
                 g[0].replay()
             return
         for i in range(n):
-            self.net.advance(self.s, self.sc)
-            sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
+            self._net_block(self.s, i)
+
+    def _net_block(self, s: dict, i: int):
+        """One network block on s, the light-phase volume after it into self.vol[i]."""
+        if self.vpart is not None:
+            self.net.advance(s, self.sc, self.vpart, self.vol[i:i + 1])
+        else:
+            self.net.advance(s, self.sc)
+            sur_light_volume(s["phi"], self.part, self.vol[i:i + 1], self.lat.stream)
 
     def _capture(self, n: int):
         import torch
@@ -649,16 +677,14 @@ class Hybrid:
         # first-call work (the network's buffers) outside the capture, on a copy
         with torch.cuda.stream(st):
             tmp = {k: v.clone() for k, v in self.s.items()}
-        self.net.advance(tmp, self.sc)
-        sur_light_volume(tmp["phi"], self.part, self.vol[:1], st)
+        self._net_block(tmp, 0)
         st.synchronize()
         del tmp
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=st):
             for i in range(n):
-                self.net.advance(self.s, self.sc)
-                sur_light_volume(self.s["phi"], self.part, self.vol[i:i + 1], st)
-        keep = [*self.s.values(), self.part, self.vol, *self.net._buf.values(), *self.net.Wb, *self.net.b]
+                self._net_block(self.s, i)
+        keep = [*self.s.values(), self.part, self.vol, self.vpart, *self.net._buf.values(), *self.net.Wb, *self.net.b]
         return g, keep
 
     def _lbm_block(self, lat_current: bool):

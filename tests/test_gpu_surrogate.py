@@ -356,6 +356,56 @@ def test_conv_advance_fused(relu_in, dil, W, stream):
         assert np.abs(got - want).max() <= 1e-5 * (np.abs(want).max() + 1.0), k
 
 
+@pytest.mark.parametrize("H,W,dil", [(37, 45, 1), (64, 96, 4), (200, 64, 16), (1024, 256, 1)])
+def test_conv_advance_volume(H, W, dil, stream):
+    """The output layer that also sums the light-phase volume
+    (sur_conv3x3_advance_volume) leaves the state bitwise as
+    sur_conv3x3_advance does and writes sur_light_volume's value of the
+    updated phi within 1e-13 relative (FP64 sums in another order); on
+    ragged and whole segments and on the largest grid (256 x 1024: one
+    partial per resident workgroup).  Two calls in a row on one partials
+    buffer, the second on a smaller frame, and the second again: the same sum,
+    bitwise."""
+    announce("conv_advance_volume", H, W, dil)
+    rng = np.random.default_rng(H + W + dil)
+    cfg = _cfg_scales()
+    sc = sur.scales_of(cfg, (0.01, 0.02, 0.03, 0.04, 0.05))
+    x = cr.bf16_round(rng.standard_normal((1, H, W, 32)))
+    w = cr.bf16_round(0.2 * rng.standard_normal((32, 9, 32)))
+    b = rng.standard_normal(32).astype(np.float32)
+    f0 = _rand_state(rng, H, W)
+    xd, wd, bd = dev(stream, t_bf16(x), t_bf16(w), t_f32(b))
+    part = torch.empty(8 * sur.VOLUME_PARTS, dtype=torch.float64, device="cuda")
+    lpart = torch.empty(8 * 256, dtype=torch.float64, device="cuda")
+    vol = torch.zeros(4, dtype=torch.float64, device="cuda")
+    small = {k: v[:H // 2].clone() for k, v in f0.items()}
+    xs = xd[:, :H // 2].contiguous()
+    g1 = {k: v.clone() for k, v in f0.items()}
+    g2 = {k: v.clone() for k, v in f0.items()}
+    s1 = {k: v.clone() for k, v in small.items()}
+    s2 = {k: v.clone() for k, v in small.items()}
+    dev(stream, part, lpart, vol, xs, *g1.values(), *g2.values(), *s1.values(), *s2.values())
+    sur.sur_conv3x3_advance(xd, wd, bd, True, sc, g1, stream, dil)
+    sur.sur_conv3x3_advance_volume(xd, wd, bd, True, sc, g2, part, vol[0:1], stream, dil)
+    sur.sur_light_volume(g1["phi"], lpart, vol[1:2], stream)
+    sur.sur_conv3x3_advance(xs, wd, bd, True, sc, s1, stream, dil)
+    sur.sur_conv3x3_advance_volume(xs, wd, bd, True, sc, s2, part, vol[2:3], stream, dil)
+    sur.sur_light_volume(s1["phi"], lpart, vol[3:4], stream)
+    stream.synchronize()
+    for k in sur.FIELDS:
+        assert torch.equal(g1[k], g2[k]), k
+        assert torch.equal(s1[k], s2[k]), k
+    v = vol.cpu().numpy()
+    assert abs(v[0] - v[1]) <= 1e-13 * abs(v[1]), (v[0], v[1])
+    assert abs(v[2] - v[3]) <= 1e-13 * abs(v[3]), (v[2], v[3])
+    # the same call again on the same input gives the same sum, bitwise
+    s3 = {k: v.clone() for k, v in small.items()}
+    dev(stream, *s3.values())
+    sur.sur_conv3x3_advance_volume(xs, wd, bd, True, sc, s3, part, vol[0:1], stream, dil)
+    stream.synchronize()
+    assert vol[0].item() == v[2]
+
+
 def test_generate_pairs_uneven_equals_single_lattices():
     """Training pairs from the batched generator (autotuned launch on lattices
     of uneven size) equal, bitwise, the pairs built from each lattice stepped

@@ -90,6 +90,21 @@ def test_conv3x3_advance_rejects(args, words):
     _rejects(rc, words)
 
 
+@pytest.mark.parametrize("args,words", [
+    (dict(part=None), "bad arguments"),
+    (dict(vol=None), "bad arguments"),
+    (dict(dil=17, w=64), "1 <= dil <= min(w, 16)"),
+    (dict(part=C.c_void_p(0x100004)), "8-byte aligned"),
+])
+def test_conv3x3_advance_volume_rejects(args, words):
+    a = dict(d_in=A, d_w=A, dil=1, h=8, w=64, part=A, vol=A)
+    a.update(args)
+    sc = _scales()
+    rc = _lib().sur_conv3x3_advance_volume(a["d_in"], a["d_w"], None, 1, a["dil"], a["h"], a["w"], C.byref(sc),
+                                           _state(), a["part"], a["vol"], None)
+    _rejects(rc, words)
+
+
 def judge_max_groups():
     """SUR_JUDGE_MAX_GROUPS as the header defines it."""
     hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "surrogate.h")
